@@ -1,0 +1,200 @@
+"""Benchmark: DCDS motion estimation on 1920x1088 synthetic video, one MI355X.
+
+One step = the whole search over one batch: DCDS (16x16 blocks, range +-15)
+over all 59 frame pairs of a 60-frame 1920x1088 uint8 sequence, one library
+call (frames resident in HBM before timing starts).  FS, DCDS on 8x8 blocks and
+simplified DCDS run over the same frames in their own timed loops and are
+reported beside it with their search points, SAD and SAD/FS.
+
+Prints one JSON line.  `value` is DCDS macroblocks per second.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "macroblocks/s at 1080p ±15 (DCDS vs FS vs learned-start), avg SAD pts/MB, SAD/FS"
+HBM_PEAK_GBS = 8000.0
+W, H, FRAMES, BLOCK, RANGE = 1920, 1088, 60, 16, 15
+# Algorithmic HBM bytes per block and launch: the current block and its
+# reference block once each, plus 12 bytes of outputs (mv, sad, nsp).
+BYTES_PER_BLOCK = lambda b: 2 * b * b + 12  # noqa: E731
+
+
+def src_digest() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_0806_0689_amd", "csrc")
+    for fn in sorted(os.listdir(d)):
+        with open(os.path.join(d, fn), "rb") as f:
+            h.update(fn.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def time_launches(fn, steps, warmup, torch):
+    """Per-launch durations (ms) from HIP events on the launch stream."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        starts[i].record()
+        fn()
+        ends[i].record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    per = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    return wall / steps, sum(per) / len(per), per
+
+
+def traffic_for(kernel: str):
+    """HBM bytes per launch measured by rocprofv3 counters, if taken on this source."""
+    p = os.path.join(ROOT, "profiles", "traffic_%s.json" % kernel)
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        rec = json.load(f)
+    if rec.get("src_digest") != src_digest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(seq, budget_s=12.0):
+    """The CPU oracle (single thread, as written) on the same workload."""
+    import oracle
+    oracle.lib()
+    n_blocks = 0
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        for p in range(FRAMES - 1):
+            oracle.dcds(seq[p + 1], seq[p], BLOCK, RANGE)
+            n_blocks += (W // BLOCK) * (H // BLOCK)
+        reps += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    dcds = {"value": n_blocks / dt, "unit": "MB/s", "cores": 1, "kind": "oracle",
+            "sample": "DCDS over all %d pairs of the same 1920x1088 sequence, %d passes (%.1f s), "
+                      "gcc -O2 scalar C, one thread" % (FRAMES - 1, reps, dt)}
+    t0 = time.perf_counter()
+    oracle.fullsearch(seq[1], seq[0], BLOCK, RANGE)
+    fs_dt = time.perf_counter() - t0
+    dcds["fs_value"] = (W // BLOCK) * (H // BLOCK) / fs_dt
+    dcds["fs_sample"] = "FS on pair 0 only (%.1f s)" % fs_dt
+    return dcds
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--only", default="", help="comma list of legs to run (dcds,fs,dcds8,dcds_s)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(blocks are independent; see the design notes on sharding).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_0806_0689_amd as me
+    from synth import make_config
+
+    t0 = time.perf_counter()
+    seq_np = make_config(3)
+    print("# generated %s in %.1f s" % (seq_np.shape, time.perf_counter() - t0), file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    seq = torch.from_numpy(seq_np).to(dev)
+    cur, ref = seq[1:], seq[:-1]
+    P = FRAMES - 1
+    legs = set(args.only.split(",")) if args.only else {"dcds", "fs", "dcds8", "dcds_s"}
+
+    results = {}
+
+    def leg(name, fn, steps, blocks_per_step):
+        outs = fn()
+        torch.cuda.synchronize()
+        ms_wall, ms_ev, per = time_launches(fn, steps, args.warmup, torch)
+        mv, sad, nsp = outs
+        results[name] = {
+            "mb_per_s": blocks_per_step / (ms_ev * 1e-3),
+            "ms_per_step": ms_ev,
+            "ms_per_step_wall": ms_wall,
+            "nsp_mean": float(nsp.double().mean()),
+            "sad_mean": float(sad.double().mean()),
+            "_sad": sad,
+        }
+        print("# %s: %.4f ms/step (events), %.4f ms wall, %.3g MB/s, nsp %.3f, sad %.1f" % (
+            name, ms_ev, ms_wall, results[name]["mb_per_s"], results[name]["nsp_mean"],
+            results[name]["sad_mean"]), file=sys.stderr, flush=True)
+
+    blocks16 = P * (H // 16) * (W // 16)
+    blocks8 = P * (H // 8) * (W // 8)
+    leg("dcds", lambda: me.dcds(cur, ref, 16, RANGE), args.steps, blocks16)
+    if "fs" in legs:
+        leg("fs", lambda: me.fullsearch(cur, ref, 16, RANGE), max(3, min(args.steps, 10)), blocks16)
+    if "dcds8" in legs:
+        leg("dcds8", lambda: me.dcds(cur, ref, 8, RANGE), args.steps, blocks8)
+    if "dcds_s" in legs:
+        leg("dcds_s", lambda: me.dcds(cur, ref, 16, RANGE, algo=me.ME_ALGO_DCDS_S), args.steps, blocks16)
+    if "fs" in legs:
+        fs_sad = results["fs"]["sad_mean"]
+        for k in ("dcds", "dcds_s"):
+            if k in results:
+                results[k]["sad_over_fs"] = results[k]["sad_mean"] / fs_sad
+    for r in results.values():
+        r.pop("_sad", None)
+
+    d = results["dcds"]
+    bytes_launch = BYTES_PER_BLOCK(16) * blocks16
+    achieved = bytes_launch / (d["ms_per_step"] * 1e-3) / 1e9
+    line = {
+        "metric": METRIC,
+        "value": d["mb_per_s"],
+        "unit": "MB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": d["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {
+            "workload": "DCDS, 1920x1088 uint8 luma, 60 frames (59 pairs, one launch), 16x16 blocks, range +-15",
+            "frames": FRAMES, "pairs": P, "block": 16, "range": RANGE, "blocks_per_step": blocks16,
+            "generator": "synth config 3, seed 3",
+        },
+        "algos": results,
+        "roofline": {
+            "kernel": "k_dcds<16,4,1>",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "bytes_per_block": BYTES_PER_BLOCK(16),
+            "traffic": traffic_for("k_dcds_1080p"),
+        },
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(seq_np)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

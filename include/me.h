@@ -1,0 +1,131 @@
+/*
+ * me.h -- block-matching motion estimation on AMD Instinct MI355X (gfx950).
+ *
+ * The problem (Jia & Zhang, §I): a frame is cut into non-overlapping,
+ * equal-sized B x B blocks; for each block of the current frame, find the
+ * displacement of the best-matching block of the reference (previous) frame
+ * inside a window centred on the block's own position, by minimising a block
+ * distortion measure.  This library uses SAD (the paper's MAD times B^2: the
+ * same argmin and the same ties).
+ *
+ * Two searches:
+ *   full search (FS): every candidate of the window (§I);
+ *   directional cross diamond search (DCDS, §III-B): a horizontal cross
+ *   pattern first, then horizontal/vertical diamonds until the centre wins,
+ *   then the two middle points.
+ *
+ * Conventions shared by every entry point
+ *   - Frames are 8-bit luma, row-major, `pitch` bytes between rows, in device
+ *     memory owned by the caller.  width and height must be multiples of
+ *     `block`; pitch must be >= width and a multiple of 4; frame pointers must
+ *     be 4-byte aligned.
+ *   - A motion vector (x, y) places the reference block at (x0 + x, y0 + y)
+ *     for the current block at (x0, y0); +x right, +y down.
+ *   - Candidate set of a block: |x|, |y| <= range and the displaced block wholly
+ *     inside the frame (restricted vectors, no padding).  Points outside it are
+ *     never evaluated and never counted.
+ *   - nsp = number of distinct candidates whose SAD was evaluated (the paper's
+ *     NSP, §III-B Eq. (8), §IV).
+ *   - FS tie order: smallest (SAD, |x|+|y|, y, x).  DCDS ties keep the pattern
+ *     centre; among other points the order is: cross (0,0), (-1,0), (+1,0),
+ *     (-2,0), (+2,0), (0,-1), (0,+1); horizontal diamond (-2,0), (+2,0), (0,-1),
+ *     (0,+1); vertical diamond (0,-2), (0,+2), (-1,0), (+1,0); middle points
+ *     negative side first.
+ *   - Sequences: a call covers `n_pairs` frame pairs; pair p reads
+ *     cur + p * pair_stride and ref + p * pair_stride (bytes).  For a sequence
+ *     stored as frames [T][height][pitch], pass cur = frame 1, ref = frame 0,
+ *     pair_stride = height * pitch and n_pairs = T - 1.
+ *   - Outputs are device arrays of n_pairs * (height/block) * (width/block)
+ *     entries in pair-major, then raster block order, owned by the caller.
+ *   - Calls are asynchronous and ordered on `stream` (a hipStream_t; NULL is
+ *     the default stream).  Outputs are valid once the stream has reached the
+ *     call.
+ *   - Argument errors are detected on the host before anything is launched;
+ *     no exception crosses this interface.  A call with n_pairs == 0 (or
+ *     n == 0) does nothing and returns ME_OK once the sizes are valid; its
+ *     pointers may then be NULL.
+ */
+#ifndef ME_H
+#define ME_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int16_t x, y;
+} me_mv;
+
+/* Status codes.  Every entry point returns one of these.                    */
+enum {
+    ME_OK = 0,
+    ME_EINVAL = -1,       /* NULL pointer, bad size, misaligned pointer or pitch */
+    ME_EUNSUPPORTED = -2, /* block not 8 or 16, range outside 1..31, ...        */
+    ME_ENOMEM = -3,       /* the library could not allocate its workspace       */
+    ME_EDEVICE = -4       /* a HIP launch or runtime call failed                */
+};
+
+/* Search algorithms.                                                        */
+enum {
+    ME_ALGO_FS = 0,     /* full search                                         */
+    ME_ALGO_DCDS = 1,   /* DCDS, §III-B                                         */
+    ME_ALGO_DCDS_S = 2  /* simplified DCDS, §IV-C: one middle point in Step 4   */
+};
+
+/* Human-readable text for a status code (static storage).                   */
+const char *me_status_string(int status);
+
+/*
+ * Full search (§I; Table IX row "FS").  Every candidate of the window is
+ * evaluated; mv/sad hold the tie-ordered minimum, nsp the candidate count.
+ */
+int me_fullsearch(const uint8_t *cur, const uint8_t *ref, int32_t width, int32_t height, int32_t pitch,
+                  int64_t pair_stride, int32_t n_pairs, int32_t block, int32_t range,
+                  me_mv *mv, uint32_t *sad, uint32_t *nsp, void *stream);
+
+/*
+ * DCDS (§III-B, Steps 1-4 with switching strategies one and two), from the
+ * window origin.
+ */
+int me_dcds(const uint8_t *cur, const uint8_t *ref, int32_t width, int32_t height, int32_t pitch,
+            int64_t pair_stride, int32_t n_pairs, int32_t block, int32_t range,
+            me_mv *mv, uint32_t *sad, uint32_t *nsp, void *stream);
+
+/*
+ * DCDS with options.  algo: ME_ALGO_DCDS or ME_ALGO_DCDS_S.
+ * start (optional, device, one per block): a proposed start vector, clamped
+ * into the block's candidate set.  The origin and the start are evaluated; if
+ * the start is the origin or its SAD is not below the origin's, plain DCDS runs
+ * from the origin (the fallback); otherwise the first cross is centred on the
+ * start.  orient (optional, device, one byte per block): 0 = horizontal cross
+ * (the paper's), 1 = vertical cross for that first pattern.  nsp counts the
+ * probe points too.  The learned start is this library's addition, not part of
+ * the paper's method.
+ */
+int me_dcds_ex(const uint8_t *cur, const uint8_t *ref, int32_t width, int32_t height, int32_t pitch,
+               int64_t pair_stride, int32_t n_pairs, int32_t block, int32_t range, int32_t algo,
+               const me_mv *start, const uint8_t *orient,
+               me_mv *mv, uint32_t *sad, uint32_t *nsp, void *stream);
+
+/*
+ * DCDS over caller-given cost surfaces instead of frames: the ideal-condition
+ * analysis of §III-C (Table VII) runs the search on a distortion defined for
+ * every window point.  cost: device int32 [n][2*range+1][2*range+1] (row = y +
+ * range, column = x + range); valid: optional device uint8 of the same shape
+ * (0 = outside the candidate set; NULL = whole window).  The set is taken
+ * as the bounding rectangle of the marked points plus the origin, which is
+ * always a candidate (frame clipping always yields such a rectangle).  start/orient as in
+ * me_dcds_ex (one per surface, optional).  Outputs per surface: mv, the
+ * distortion at mv (cost_out) and nsp.  Costs must lie in 0 .. 2^28 - 1.
+ */
+int me_dcds_surface(const int32_t *cost, const uint8_t *valid, int32_t n, int32_t range, int32_t algo,
+                    const me_mv *start, const uint8_t *orient,
+                    me_mv *mv, uint32_t *cost_out, uint32_t *nsp, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ME_H */

@@ -1,0 +1,196 @@
+"""Block-matching motion estimation (FS and DCDS) on AMD MI355X.
+
+Python binding of ``libme.so`` (``include/me.h``).  This module only marshals
+arguments: every step of a search runs in the library's HIP kernels.  PyTorch
+provides device memory and streams.  There is no CPU fallback: if the library
+is not built, every call raises.
+
+Low-level functions carry the C names (``me_fullsearch``, ``me_dcds``,
+``me_dcds_ex``, ``me_dcds_surface``) and take raw pointers and sizes.  The
+helpers ``fullsearch``, ``dcds`` and ``dcds_surface`` take torch tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libme.so")
+
+ME_OK = 0
+ME_EINVAL = -1
+ME_EUNSUPPORTED = -2
+ME_ENOMEM = -3
+ME_EDEVICE = -4
+
+ME_ALGO_FS = 0
+ME_ALGO_DCDS = 1
+ME_ALGO_DCDS_S = 2
+
+# Every symbol include/me.h declares (checked by the ABI tests).
+EXPORTS = [
+    "me_status_string",
+    "me_fullsearch",
+    "me_dcds",
+    "me_dcds_ex",
+    "me_dcds_surface",
+]
+
+
+class MEError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__("%s: %s (%d)" % (where, status_string(status), status))
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libme.so is not built (run __graft_entry__.build()); there is no fallback path")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.me_status_string.argtypes = [ctypes.c_int]
+        L.me_status_string.restype = ctypes.c_char_p
+        frame = [vp, vp, i32, i32, i32, i64, i32, i32, i32]
+        L.me_fullsearch.argtypes = frame + [vp, vp, vp, vp]
+        L.me_fullsearch.restype = ctypes.c_int
+        L.me_dcds.argtypes = frame + [vp, vp, vp, vp]
+        L.me_dcds.restype = ctypes.c_int
+        L.me_dcds_ex.argtypes = frame + [i32, vp, vp, vp, vp, vp, vp]
+        L.me_dcds_ex.restype = ctypes.c_int
+        L.me_dcds_surface.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]
+        L.me_dcds_surface.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().me_status_string(int(status)).decode()
+
+
+# ----------------------------------------------------------------------------
+# Raw C entry points (pointers as ints, sizes as ints, stream handle as int).
+# ----------------------------------------------------------------------------
+def me_fullsearch(cur, ref, width, height, pitch, pair_stride, n_pairs, block, range_, mv, sad, nsp, stream=0):
+    return lib().me_fullsearch(cur, ref, width, height, pitch, pair_stride, n_pairs, block, range_, mv, sad, nsp,
+                               stream)
+
+
+def me_dcds(cur, ref, width, height, pitch, pair_stride, n_pairs, block, range_, mv, sad, nsp, stream=0):
+    return lib().me_dcds(cur, ref, width, height, pitch, pair_stride, n_pairs, block, range_, mv, sad, nsp, stream)
+
+
+def me_dcds_ex(cur, ref, width, height, pitch, pair_stride, n_pairs, block, range_, algo, start, orient, mv, sad,
+               nsp, stream=0):
+    return lib().me_dcds_ex(cur, ref, width, height, pitch, pair_stride, n_pairs, block, range_, algo, start,
+                            orient, mv, sad, nsp, stream)
+
+
+def me_dcds_surface(cost, valid, n, range_, algo, start, orient, mv, cost_out, nsp, stream=0):
+    return lib().me_dcds_surface(cost, valid, n, range_, algo, start, orient, mv, cost_out, nsp, stream)
+
+
+# ----------------------------------------------------------------------------
+# Tensor helpers.
+# ----------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _frames(cur, ref):
+    """Accepts [H, W] or [P, H, W] uint8 CUDA tensors with unit column stride."""
+    torch = _torch()
+    if cur.dtype != torch.uint8 or ref.dtype != torch.uint8:
+        raise TypeError("frames must be uint8")
+    if not cur.is_cuda or not ref.is_cuda:
+        raise TypeError("frames must be on the GPU")
+    if cur.shape != ref.shape or cur.dim() not in (2, 3):
+        raise ValueError("cur and ref must both be [H, W] or [P, H, W]")
+    if cur.stride() != ref.stride() or cur.stride(-1) != 1:
+        raise ValueError("cur and ref must share strides, with unit column stride")
+    if cur.dim() == 2:
+        P, (H, W) = 1, cur.shape
+        stride = H * cur.stride(0)
+    else:
+        P, H, W = cur.shape
+        stride = cur.stride(0)
+    return P, H, W, cur.stride(-2), stride
+
+
+def _outputs(P, hb, wb, device, out):
+    torch = _torch()
+    if out is not None:
+        return out
+    mv = torch.empty((P, hb, wb, 2), dtype=torch.int16, device=device)
+    sad = torch.empty((P, hb, wb), dtype=torch.int32, device=device)
+    nsp = torch.empty((P, hb, wb), dtype=torch.int32, device=device)
+    return mv, sad, nsp
+
+
+def _check(rc, where):
+    if rc != ME_OK:
+        raise MEError(rc, where)
+
+
+def sequence_pairs(seq):
+    """Views (cur, ref) = (frames 1.., frames ..-1) of a [T, H, W] sequence."""
+    return seq[1:], seq[:-1]
+
+
+def fullsearch(cur, ref, block=16, range_=7, out=None, stream=None):
+    """FS on one pair ([H, W]) or P pairs ([P, H, W]); returns (mv, sad, nsp) as
+    [P, H/B, W/B, 2] int16 and [P, H/B, W/B] int32 tensors."""
+    P, H, W, pitch, stride = _frames(cur, ref)
+    mv, sad, nsp = _outputs(P, H // block, W // block, cur.device, out)
+    rc = me_fullsearch(cur.data_ptr(), ref.data_ptr(), W, H, pitch, stride, P, block, range_, mv.data_ptr(),
+                       sad.data_ptr(), nsp.data_ptr(), _stream(stream))
+    _check(rc, "me_fullsearch")
+    return mv, sad, nsp
+
+
+def dcds(cur, ref, block=16, range_=7, algo=ME_ALGO_DCDS, start=None, orient=None, out=None, stream=None):
+    """DCDS (or DCDS^S with algo=ME_ALGO_DCDS_S), optionally from per-block start
+    vectors (int16 [P, H/B, W/B, 2]) and first-cross orientations (uint8)."""
+    P, H, W, pitch, stride = _frames(cur, ref)
+    mv, sad, nsp = _outputs(P, H // block, W // block, cur.device, out)
+    sp = start.data_ptr() if start is not None else None
+    op = orient.data_ptr() if orient is not None else None
+    rc = me_dcds_ex(cur.data_ptr(), ref.data_ptr(), W, H, pitch, stride, P, block, range_, algo, sp, op,
+                    mv.data_ptr(), sad.data_ptr(), nsp.data_ptr(), _stream(stream))
+    _check(rc, "me_dcds_ex")
+    return mv, sad, nsp
+
+
+def dcds_surface(cost, valid=None, algo=ME_ALGO_DCDS, start=None, orient=None, stream=None):
+    """DCDS over int32 cost surfaces [n, 2R+1, 2R+1] (device); returns (mv, cost, nsp)."""
+    torch = _torch()
+    if cost.dtype != torch.int32 or cost.dim() != 3 or not cost.is_contiguous():
+        raise ValueError("cost must be a contiguous int32 [n, 2R+1, 2R+1] tensor")
+    n, side, side2 = cost.shape
+    if side != side2 or side % 2 != 1:
+        raise ValueError("surfaces must be square with odd side")
+    mv = torch.empty((n, 2), dtype=torch.int16, device=cost.device)
+    cout = torch.empty((n,), dtype=torch.int32, device=cost.device)
+    nsp = torch.empty((n,), dtype=torch.int32, device=cost.device)
+    vp = valid.data_ptr() if valid is not None else None
+    sp = start.data_ptr() if start is not None else None
+    op = orient.data_ptr() if orient is not None else None
+    rc = me_dcds_surface(cost.data_ptr(), vp, n, side // 2, algo, sp, op, mv.data_ptr(), cout.data_ptr(),
+                         nsp.data_ptr(), _stream(stream))
+    _check(rc, "me_dcds_surface")
+    return mv, cout, nsp

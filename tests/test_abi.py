@@ -1,0 +1,110 @@
+"""The C ABI (include/me.h): the library loads without a GPU, exports every
+declared symbol, and rejects bad arguments on the host before any launch
+(these calls return before touching the device, so they run on the CPU)."""
+import os
+import re
+
+import pytest
+
+import paper_0806_0689_amd as me
+from conftest import ROOT
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(me_[a-z_0-9]+)\s*\(", text))
+    return names
+
+
+def test_every_declared_symbol_is_exported():
+    L = me.lib()
+    declared = _declared()
+    assert declared, "no declarations found"
+    for name in sorted(declared):
+        assert hasattr(L, name), name
+    assert declared == set(me.EXPORTS)
+
+
+def test_status_strings():
+    for s in (me.ME_OK, me.ME_EINVAL, me.ME_EUNSUPPORTED, me.ME_ENOMEM, me.ME_EDEVICE):
+        assert me.status_string(s)
+    assert me.status_string(12345) == "unknown status"
+
+
+# A fake but 4-aligned "device" address: only reached by calls that must fail
+# their host-side checks (or do nothing), never dereferenced.
+P = 0x1000
+
+
+def _frame_call(fn, **kw):
+    a = dict(cur=P, ref=P, width=64, height=32, pitch=64, pair_stride=64 * 32, n_pairs=1, block=16, range_=7,
+             mv=P, sad=P, nsp=P)
+    a.update(kw)
+    return fn(a["cur"], a["ref"], a["width"], a["height"], a["pitch"], a["pair_stride"], a["n_pairs"], a["block"],
+              a["range_"], a["mv"], a["sad"], a["nsp"], 0)
+
+
+@pytest.mark.parametrize("fn", [me.me_fullsearch, me.me_dcds])
+@pytest.mark.parametrize("kw,status", [
+    (dict(cur=None), me.ME_EINVAL),
+    (dict(ref=None), me.ME_EINVAL),
+    (dict(mv=None), me.ME_EINVAL),
+    (dict(sad=None), me.ME_EINVAL),
+    (dict(nsp=None), me.ME_EINVAL),
+    (dict(width=0), me.ME_EINVAL),
+    (dict(height=-16), me.ME_EINVAL),
+    (dict(n_pairs=-1), me.ME_EINVAL),
+    (dict(width=72), me.ME_EINVAL),           # not a multiple of the block
+    (dict(height=40), me.ME_EINVAL),
+    (dict(pitch=60), me.ME_EINVAL),           # pitch < width
+    (dict(pitch=66), me.ME_EINVAL),           # pitch not a multiple of 4
+    (dict(cur=P + 2), me.ME_EINVAL),          # misaligned frame
+    (dict(ref=P + 1), me.ME_EINVAL),
+    (dict(pair_stride=6), me.ME_EINVAL),
+    (dict(block=12), me.ME_EUNSUPPORTED),
+    (dict(block=32), me.ME_EUNSUPPORTED),
+    (dict(range_=0), me.ME_EUNSUPPORTED),
+    (dict(range_=32), me.ME_EUNSUPPORTED),
+    (dict(n_pairs=0), me.ME_OK),              # empty input: nothing to do
+    (dict(n_pairs=0, cur=None, mv=None), me.ME_OK),
+    (dict(n_pairs=0, block=12), me.ME_EUNSUPPORTED),
+])
+def test_frame_argument_checks(fn, kw, status):
+    assert _frame_call(fn, **kw) == status
+
+
+def test_dcds_ex_checks():
+    base = (P, P, 64, 32, 64, 2048, 1, 16, 7)
+    assert me.me_dcds_ex(*base, 7, None, None, P, P, P, 0) == me.ME_EUNSUPPORTED  # unknown algo
+    assert me.me_dcds_ex(*base, me.ME_ALGO_FS, None, None, P, P, P, 0) == me.ME_EUNSUPPORTED
+    assert me.me_dcds_ex(*base, me.ME_ALGO_DCDS, None, P, P, P, P, 0) == me.ME_EINVAL  # orient without start
+    assert me.me_dcds_ex(P, P, 64, 32, 64, 2048, 0, 16, 7, me.ME_ALGO_DCDS_S, P, P, P, P, P, 0) == me.ME_OK
+
+
+def test_surface_checks():
+    assert me.me_dcds_surface(None, None, 1, 7, 1, None, None, P, P, P, 0) == me.ME_EINVAL
+    assert me.me_dcds_surface(P, None, -1, 7, 1, None, None, P, P, P, 0) == me.ME_EINVAL
+    assert me.me_dcds_surface(P, None, 1, 0, 1, None, None, P, P, P, 0) == me.ME_EUNSUPPORTED
+    assert me.me_dcds_surface(P, None, 1, 7, 0, None, None, P, P, P, 0) == me.ME_EUNSUPPORTED
+    assert me.me_dcds_surface(P, None, 1, 7, 1, None, P, P, P, P, 0) == me.ME_EINVAL
+    assert me.me_dcds_surface(P, None, 0, 7, 1, None, None, P, P, P, 0) == me.ME_OK
+
+
+def test_product_path_does_not_import_the_oracle():
+    """The HIP package and the oracle share no code and neither imports the other."""
+    pkg = os.path.join(ROOT, "paper_0806_0689_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, fn)).read()
+                assert not re.search(r"^\s*(import|from)\s+oracle\b", text, re.M), fn
+                assert "me_oracle" not in text, fn
+    for fn in os.listdir(os.path.join(ROOT, "oracle")):
+        if fn.endswith((".py", ".c", ".h")):
+            text = open(os.path.join(ROOT, "oracle", fn)).read()
+            assert not re.search(r"^\s*(import|from)\s+paper_0806_0689_amd\b", text, re.M), fn
+            assert '#include "me' not in text and "csrc" not in text, fn
