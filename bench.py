@@ -99,7 +99,11 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", default="", help="comma list of legs to run (dcds,fs,dcds8,dcds_s)")
+    ap.add_argument("--only", default="", help="comma list of extra legs to run (fs,dcds8,dcds_s); dcds always runs")
+    ap.add_argument("--sweep", action="store_true",
+                    help="time every DCDS kernel configuration (rows per lane x waves per group) and exit")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first copy 256 MiB device-to-device (a known-size kernel for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -120,6 +124,27 @@ def main():
     cur, ref = seq[1:], seq[:-1]
     P = FRAMES - 1
     legs = set(args.only.split(",")) if args.only else {"dcds", "fs", "dcds8", "dcds_s"}
+    if args.calib_copy:
+        src = torch.ones(256 << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    if args.sweep:
+        for B, rpls in ((16, (1, 2, 4)), (8, (1, 2))):
+            for rpl in rpls:
+                for wpg in (1, 2, 4):
+                    if me.me_set_config(B, RANGE, (rpl, wpg)) != me.ME_OK:
+                        continue
+                    fn = lambda: me.dcds(cur, ref, B, RANGE)  # noqa: E731
+                    fn()
+                    _, ms, _ = time_launches(fn, args.steps, args.warmup, torch)
+                    nb = P * (H // B) * (W // B)
+                    print(json.dumps({"block": B, "rows_per_lane": rpl, "waves_per_group": wpg, "ms": ms,
+                                      "mb_per_s": nb / (ms * 1e-3)}), flush=True)
+            me.me_set_config(B, RANGE, None)
+        return
 
     results = {}
 

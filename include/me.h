@@ -78,6 +78,26 @@ enum {
 const char *me_status_string(int status);
 
 /*
+ * Kernel configuration of the DCDS searches (me_dcds, me_dcds_ex): how many
+ * rows of a block one lane holds (1, 2 or 4 for 16x16 blocks; 1 or 2 for 8x8)
+ * and how many waves share one staged reference window (1, 2 or 4; each wave
+ * takes 64 * rows_per_lane / block blocks side by side).  Results do not
+ * depend on it, only speed.  Kept per block size and range class (1-7, 8-15,
+ * 16-31) for the process; me_set_config with cfg == NULL restores the
+ * built-in default; ME_EUNSUPPORTED for values outside the lists (and, at call
+ * time, for a configuration whose window exceeds the 160 KiB of LDS of a
+ * compute unit).  Not meant to
+ * change while searches of that class are being enqueued from another thread.
+ */
+typedef struct {
+    int32_t rows_per_lane;
+    int32_t waves_per_group;
+} me_config;
+
+int me_set_config(int32_t block, int32_t range, const me_config *cfg);
+int me_get_config(int32_t block, int32_t range, me_config *cfg);
+
+/*
  * Full search (§I; Table IX row "FS").  Every candidate of the window is
  * evaluated; mv/sad hold the tie-ordered minimum, nsp the candidate count.
  */

@@ -30,11 +30,17 @@ ME_ALGO_DCDS_S = 2
 # Every symbol include/me.h declares (checked by the ABI tests).
 EXPORTS = [
     "me_status_string",
+    "me_set_config",
+    "me_get_config",
     "me_fullsearch",
     "me_dcds",
     "me_dcds_ex",
     "me_dcds_surface",
 ]
+
+
+class MeConfig(ctypes.Structure):
+    _fields_ = [("rows_per_lane", ctypes.c_int32), ("waves_per_group", ctypes.c_int32)]
 
 
 class MEError(RuntimeError):
@@ -65,6 +71,10 @@ def lib() -> ctypes.CDLL:
         L.me_dcds_ex.restype = ctypes.c_int
         L.me_dcds_surface.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]
         L.me_dcds_surface.restype = ctypes.c_int
+        L.me_set_config.argtypes = [i32, i32, ctypes.POINTER(MeConfig)]
+        L.me_set_config.restype = ctypes.c_int
+        L.me_get_config.argtypes = [i32, i32, ctypes.POINTER(MeConfig)]
+        L.me_get_config.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -93,6 +103,23 @@ def me_dcds_ex(cur, ref, width, height, pitch, pair_stride, n_pairs, block, rang
 
 def me_dcds_surface(cost, valid, n, range_, algo, start, orient, mv, cost_out, nsp, stream=0):
     return lib().me_dcds_surface(cost, valid, n, range_, algo, start, orient, mv, cost_out, nsp, stream)
+
+
+def me_set_config(block, range_, cfg):
+    """cfg: (rows_per_lane, waves_per_group) or None for the default."""
+    p = None if cfg is None else ctypes.byref(MeConfig(int(cfg[0]), int(cfg[1])))
+    return lib().me_set_config(block, range_, p)
+
+
+def me_get_config(block, range_):
+    c = MeConfig()
+    rc = lib().me_get_config(block, range_, ctypes.byref(c))
+    _check(rc, "me_get_config")
+    return c.rows_per_lane, c.waves_per_group
+
+
+def set_config(block, range_, cfg):
+    _check(me_set_config(block, range_, cfg), "me_set_config")
 
 
 # ----------------------------------------------------------------------------

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "me.h"
 #include "me_kernels.hpp"
 
@@ -10,9 +12,7 @@ using namespace me;
 
 namespace {
 
-constexpr int kDcdsWavesPerGroup = 4;
-
-bool aligned4(const void* p) { return ((uintptr_t)p & 3u) == 0; }
+bool aligned(const void* p, uintptr_t m) { return ((uintptr_t)p & (m - 1)) == 0; }
 
 int check_frames(const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t height, int32_t pitch,
                  int64_t pair_stride, int32_t n_pairs, int32_t block, int32_t range, const void* mv,
@@ -24,7 +24,7 @@ int check_frames(const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t 
     if (pitch < width || (pitch & 3)) return ME_EINVAL;
     if (n_pairs == 0) return ME_OK;  // nothing to read or write; pointers may be NULL
     if (!cur || !ref || !mv || !sad || !nsp) return ME_EINVAL;
-    if (!aligned4(cur) || !aligned4(ref) || (pair_stride & 3)) return ME_EINVAL;
+    if (!aligned(cur, 4) || !aligned(ref, 4) || (pair_stride & 3)) return ME_EINVAL;
     if ((int64_t)(width / block) * (height / block) * n_pairs > (int64_t)INT32_MAX) return ME_EUNSUPPORTED;
     return ME_OK;
 }
@@ -48,15 +48,89 @@ FrameArgs frame_args(const uint8_t* cur, const uint8_t* ref, int32_t width, int3
 
 int launched() { return hipGetLastError() == hipSuccess ? ME_OK : ME_EDEVICE; }
 
-template <int B, int ALGO>
-int launch_dcds(const FrameArgs& a, int32_t n_pairs, const me_mv* start, const uint8_t* orient, me_mv* mv,
-                uint32_t* sad, uint32_t* nsp, hipStream_t st) {
-    constexpr int WPG = kDcdsWavesPerGroup;
-    const size_t lds = dcds_lds_bytes<B, WPG>(a.R);
+constexpr size_t kMaxLds = 160 * 1024;  // LDS per compute unit on gfx950
+
+// ---------------------------------------------------------------------------
+// DCDS kernel configurations: rows per lane x waves per workgroup, per block
+// size and range class.  Defaults come from measurements on MI355X; the
+// autotuner may replace them.
+// ---------------------------------------------------------------------------
+int range_class(int R) { return R <= 7 ? 0 : (R <= 15 ? 1 : 2); }
+
+std::atomic<int> g_cfg[2][3];  // [block 8/16][range class] = rpl * 16 + wpg; 0 = default
+int default_cfg(int block, int rc) {
+    (void)rc;
+    return block == 16 ? (2 * 16 + 4) : (2 * 16 + 4);
+}
+int current_cfg(int block, int rc) {
+    const int v = g_cfg[block == 16][rc].load(std::memory_order_relaxed);
+    return v ? v : default_cfg(block, rc);
+}
+bool valid_cfg(int block, int rpl, int wpg) {
+    const bool r_ok = block == 16 ? (rpl == 1 || rpl == 2 || rpl == 4) : (rpl == 1 || rpl == 2);
+    return r_ok && (wpg == 1 || wpg == 2 || wpg == 4);
+}
+
+template <int B, int RPL, int WPG, int RMAX>
+int launch_dcds_cfg(const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t height, int32_t pitch,
+                    int64_t pair_stride, int32_t n_pairs, int32_t range, int flags, const me_mv* start,
+                    const uint8_t* orient, me_mv* mv, uint32_t* sad, uint32_t* nsp, hipStream_t st) {
+    using G = DcdsGeo<B, RPL, WPG, RMAX>;
+    const size_t lds = dcds_lds_bytes<B, RPL, WPG, RMAX>(range);
+    if (lds > kMaxLds) return ME_EUNSUPPORTED;
+    if (lds > 65536) {
+        // Windows above 64 KiB need the kernel's dynamic-LDS limit raised once.
+        static std::atomic<int> raised{0};
+        if (!raised.load()) {
+            if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dcds<B, RPL, WPG, RMAX>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds) != hipSuccess)
+                return ME_EUNSUPPORTED;
+            raised.store(1);
+        }
+    }
+    const FrameArgs a = frame_args(cur, ref, width, height, pitch, pair_stride, B, range, G::BPW, WPG);
     const long long grid = (long long)a.tiles_x * a.tiles_y * n_pairs;
-    hipLaunchKernelGGL((k_dcds<B, WPG, ALGO>), dim3((unsigned)grid), dim3(64 * WPG), lds, st, a,
+    if (grid > INT32_MAX) return ME_EUNSUPPORTED;
+    hipLaunchKernelGGL((k_dcds<B, RPL, WPG, RMAX>), dim3((unsigned)grid), dim3(64 * WPG), lds, st, a, flags,
                        reinterpret_cast<const int16_t*>(start), orient, reinterpret_cast<int16_t*>(mv), sad, nsp);
     return launched();
+}
+
+template <int B, int RPL, int RMAX>
+int launch_dcds_wpg(int wpg, const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t height, int32_t pitch,
+                    int64_t pair_stride, int32_t n_pairs, int32_t range, int flags, const me_mv* start,
+                    const uint8_t* orient, me_mv* mv, uint32_t* sad, uint32_t* nsp, hipStream_t st) {
+#define ME_ARGS cur, ref, width, height, pitch, pair_stride, n_pairs, range, flags, start, orient, mv, sad, nsp, st
+    if (wpg == 1) return launch_dcds_cfg<B, RPL, 1, RMAX>(ME_ARGS);
+    if (wpg == 2) return launch_dcds_cfg<B, RPL, 2, RMAX>(ME_ARGS);
+    return launch_dcds_cfg<B, RPL, 4, RMAX>(ME_ARGS);
+}
+
+template <int B, int RMAX>
+int launch_dcds_rpl(int rpl, int wpg, const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t height,
+                    int32_t pitch, int64_t pair_stride, int32_t n_pairs, int32_t range, int flags,
+                    const me_mv* start, const uint8_t* orient, me_mv* mv, uint32_t* sad, uint32_t* nsp,
+                    hipStream_t st) {
+    if (rpl == 1) return launch_dcds_wpg<B, 1, RMAX>(wpg, ME_ARGS);
+    if constexpr (B == 16) {
+        if (rpl == 4) return launch_dcds_wpg<B, 4, RMAX>(wpg, ME_ARGS);
+    }
+    return launch_dcds_wpg<B, 2, RMAX>(wpg, ME_ARGS);
+}
+
+int launch_dcds(int32_t block, int rpl, int wpg, const uint8_t* cur, const uint8_t* ref, int32_t width,
+                int32_t height, int32_t pitch, int64_t pair_stride, int32_t n_pairs, int32_t range, int flags,
+                const me_mv* start, const uint8_t* orient, me_mv* mv, uint32_t* sad, uint32_t* nsp, hipStream_t st) {
+    const int rc = range_class(range);
+    if (block == 16) {
+        if (rc == 0) return launch_dcds_rpl<16, 7>(rpl, wpg, ME_ARGS);
+        if (rc == 1) return launch_dcds_rpl<16, 15>(rpl, wpg, ME_ARGS);
+        return launch_dcds_rpl<16, 31>(rpl, wpg, ME_ARGS);
+    }
+    if (rc == 0) return launch_dcds_rpl<8, 7>(rpl, wpg, ME_ARGS);
+    if (rc == 1) return launch_dcds_rpl<8, 15>(rpl, wpg, ME_ARGS);
+    return launch_dcds_rpl<8, 31>(rpl, wpg, ME_ARGS);
+#undef ME_ARGS
 }
 
 }  // namespace
@@ -67,11 +141,34 @@ const char* me_status_string(int status) {
     switch (status) {
         case ME_OK: return "ok";
         case ME_EINVAL: return "invalid argument (NULL pointer, size, alignment or pitch)";
-        case ME_EUNSUPPORTED: return "unsupported block size or search range";
+        case ME_EUNSUPPORTED: return "unsupported block size, search range or configuration";
         case ME_ENOMEM: return "out of memory";
         case ME_EDEVICE: return "HIP launch or runtime error";
         default: return "unknown status";
     }
+}
+
+int me_set_config(int32_t block, int32_t range, const me_config* cfg) {
+    if (block != 8 && block != 16) return ME_EUNSUPPORTED;
+    if (range < 1 || range > 31) return ME_EUNSUPPORTED;
+    const int rc = range_class(range);
+    if (!cfg) {
+        g_cfg[block == 16][rc].store(0);
+        return ME_OK;
+    }
+    if (!valid_cfg(block, cfg->rows_per_lane, cfg->waves_per_group)) return ME_EUNSUPPORTED;
+    g_cfg[block == 16][rc].store(cfg->rows_per_lane * 16 + cfg->waves_per_group);
+    return ME_OK;
+}
+
+int me_get_config(int32_t block, int32_t range, me_config* cfg) {
+    if (!cfg) return ME_EINVAL;
+    if (block != 8 && block != 16) return ME_EUNSUPPORTED;
+    if (range < 1 || range > 31) return ME_EUNSUPPORTED;
+    const int v = current_cfg(block, range_class(range));
+    cfg->rows_per_lane = v / 16;
+    cfg->waves_per_group = v % 16;
+    return ME_OK;
 }
 
 int me_fullsearch(const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t height, int32_t pitch,
@@ -99,15 +196,12 @@ int me_dcds_ex(const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t he
     if (algo != ME_ALGO_DCDS && algo != ME_ALGO_DCDS_S) return ME_EUNSUPPORTED;
     if (orient && !start) return ME_EINVAL;
     if (n_pairs == 0) return ME_OK;
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const int tw = 64 / block;
-    const FrameArgs a =
-        frame_args(cur, ref, width, height, pitch, pair_stride, block, range, tw, kDcdsWavesPerGroup);
-    if (block == 16)
-        return algo == ME_ALGO_DCDS ? launch_dcds<16, ALGO_DCDS>(a, n_pairs, start, orient, mv, sad, nsp, st)
-                                    : launch_dcds<16, ALGO_DCDS_S>(a, n_pairs, start, orient, mv, sad, nsp, st);
-    return algo == ME_ALGO_DCDS ? launch_dcds<8, ALGO_DCDS>(a, n_pairs, start, orient, mv, sad, nsp, st)
-                                : launch_dcds<8, ALGO_DCDS_S>(a, n_pairs, start, orient, mv, sad, nsp, st);
+    int flags = algo == ME_ALGO_DCDS_S ? DCDS_SIMPLIFIED : 0;
+    if (aligned(cur, 16) && aligned(ref, 16) && (pitch % 16) == 0 && (width % 16) == 0 && (pair_stride % 16) == 0)
+        flags |= DCDS_VEC16;
+    const int cfg = current_cfg(block, range_class(range));
+    return launch_dcds(block, cfg / 16, cfg % 16, cur, ref, width, height, pitch, pair_stride, n_pairs, range, flags,
+                       start, orient, mv, sad, nsp, reinterpret_cast<hipStream_t>(stream));
 }
 
 int me_dcds(const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t height, int32_t pitch,
@@ -128,15 +222,9 @@ int me_dcds_surface(const int32_t* cost, const uint8_t* valid, int32_t n, int32_
     if (!cost || !mv || !cost_out || !nsp) return ME_EINVAL;
     const size_t lds = (size_t)4 * 16 * bitmap_words(range);
     const unsigned grid = (unsigned)((n + 15) / 16);
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    if (algo == ME_ALGO_DCDS)
-        hipLaunchKernelGGL(k_dcds_surface<ALGO_DCDS>, dim3(grid), dim3(256), lds, st, cost, valid, n, range,
-                           reinterpret_cast<const int16_t*>(start), orient, reinterpret_cast<int16_t*>(mv), cost_out,
-                           nsp);
-    else
-        hipLaunchKernelGGL(k_dcds_surface<ALGO_DCDS_S>, dim3(grid), dim3(256), lds, st, cost, valid, n, range,
-                           reinterpret_cast<const int16_t*>(start), orient, reinterpret_cast<int16_t*>(mv), cost_out,
-                           nsp);
+    hipLaunchKernelGGL(k_dcds_surface, dim3(grid), dim3(256), lds, reinterpret_cast<hipStream_t>(stream), cost, valid,
+                       n, range, algo == ME_ALGO_DCDS_S, reinterpret_cast<const int16_t*>(start), orient,
+                       reinterpret_cast<int16_t*>(mv), cost_out, nsp);
     return launched();
 }
 

@@ -1,0 +1,295 @@
+// DCDS over frame pairs.
+//
+// Layout.  A workgroup of WPG waves owns a tile of BPW x WPG blocks: each wave
+// takes BPW = 64 / L blocks side by side, each block L = B / RPL lanes, lane
+// g the rows g, g + L, ... of its block (each row's B/4 words in VGPRs).  The
+// tile's reference window, widened by RMAX + 2 rows and at least as many
+// columns on every side (so every point a pattern can reach from a valid
+// centre is in LDS), is staged once; each block keeps its visited-point bitmap
+// in LDS.  RMAX is the range class (7, 15 or 31): it fixes the window geometry
+// at compile time, the actual range R <= RMAX only bounds the candidate set.
+//
+// SAD of a point: per lane, two aligned LDS words per 4 pixels, one
+// v_alignbyte_b32 and one v_sad_u8 (or v_sad_hi_u8, which accumulates into the
+// high half so that two points share one register), then a DPP sum over the
+// block's L lanes.  The paper's first step at the origin reads its centre row
+// once: v_qsad_pk_u16_u8 gives four horizontal shifts per instruction.
+#pragma once
+
+#include "me_search.hpp"
+
+namespace me {
+
+struct FrameArgs {
+    const uint8_t* cur;
+    const uint8_t* ref;
+    long long pair_stride;  // bytes between consecutive pairs
+    int W, H, pitch;
+    int R;
+    int bw, bh;             // blocks per row / column
+    int tiles_x, tiles_y;   // tiles per row / column
+};
+
+__host__ __device__ constexpr int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+template <int B, int RPL, int WPG, int RMAX>
+struct DcdsGeo {
+    static constexpr int K = B / 4;          // words per block row
+    static constexpr int L = B / RPL;        // lanes per block
+    static constexpr int BPW = 64 / L;       // blocks per wave
+    static constexpr int TW = BPW * B;       // tile width (pixels)
+    static constexpr int TH = WPG * B;       // tile height
+    static constexpr int MR = RMAX + 2;      // rows above and below the tile
+    static constexpr int ML = round_up(MR, 16);              // bytes left of the tile
+    static constexpr int NEED = round_up(ML + TW + RMAX + 6, 16) / 4;  // words a row must hold
+    // Row pitch of 32m + 1 words: the lanes of a block read consecutive rows
+    // at one column, and blocks sit 4 words apart, so a half-wave's 32 reads
+    // fall into distinct banks.
+    static constexpr int WDW = (NEED + 30) / 32 * 32 + 1;
+    static constexpr int WR = TH + 2 * MR;   // LDS rows
+    static constexpr int WIN_WORDS = WR * WDW;
+    static_assert(L >= 2 && BPW * L == 64, "lanes per block must divide the wave");
+};
+
+__host__ __device__ constexpr int bitmap_words(int R) { return ((2 * R + 1) * (2 * R + 1) + 31) / 32; }
+
+template <int B, int RPL, int WPG, int RMAX>
+__host__ __device__ constexpr size_t dcds_lds_bytes(int R) {
+    using G = DcdsGeo<B, RPL, WPG, RMAX>;
+    return (size_t)4 * (G::WIN_WORDS + G::BPW * WPG * bitmap_words(R));
+}
+
+// Copies the tile window (rows of WB bytes, LDS pitch WDW words) of the
+// reference frame into LDS.  VEC: 16-byte global loads (frame base, pitch and
+// width multiples of 16); otherwise 4-byte loads.  Words outside the frame
+// read as 0; no valid candidate uses them.
+template <int WB, int WDW, int WR, int NT, bool VEC>
+__device__ __forceinline__ void stage(uint32_t* win, const uint8_t* frame, int W, int H, int pitch, int xs, int ys) {
+    constexpr int CH = VEC ? 16 : 4;       // bytes per chunk
+    constexpr int CPR = WB / CH;           // chunks per row
+    constexpr int RSTEP = NT / CPR;        // rows per pass
+    const int t = threadIdx.x;
+    const int c = t % CPR, r0 = t / CPR;
+    if (r0 >= RSTEP) return;
+    const int gx = xs + c * CH;
+    const bool xin = gx >= 0 && gx < W;
+    for (int r = r0; r < WR; r += RSTEP) {
+        const int gy = ys + r;
+        const bool in = xin && gy >= 0 && gy < H;
+        uint32_t* dst = win + r * WDW + c * (CH / 4);
+        if constexpr (VEC) {
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (in) v = *reinterpret_cast<const uint4*>(frame + (size_t)gy * pitch + gx);
+            dst[0] = v.x;
+            dst[1] = v.y;
+            dst[2] = v.z;
+            dst[3] = v.w;
+        } else {
+            uint32_t v = 0u;
+            if (in) v = *reinterpret_cast<const uint32_t*>(frame + (size_t)gy * pitch + gx);
+            dst[0] = v;
+        }
+    }
+}
+
+// Lane g of a block holds rows g, g + L, ..., g + (RPL - 1) L of the block.
+template <int B, int RPL, int WDW>
+struct FrameEval {
+    static constexpr int K = B / 4;
+    static constexpr int L = B / RPL;
+    static constexpr int ROWB = WDW * 4;
+    static constexpr int JW = L * WDW;  // words between a lane's rows
+    const uint8_t* lds;  // window base
+    int base;            // LDS byte offset of (this lane's first row, block column 0) at offset (0, 0)
+    uint32_t cur[RPL][K];
+
+    // Partial SAD of point (x, y) over this lane's rows, added into the low
+    // (HI = false) or high (HI = true) half of acc.
+    template <bool HI>
+    __device__ __forceinline__ uint32_t pt(int x, int y, uint32_t acc) const {
+        const int a = __mul24(y, ROWB) + x + base;
+        const uint32_t* w = reinterpret_cast<const uint32_t*>(lds + (a & ~3));
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+            uint32_t d[K + 1];
+#pragma unroll
+            for (int k = 0; k <= K; ++k) d[k] = w[j * JW + k];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const uint32_t f = __builtin_amdgcn_alignbyte(d[k + 1], d[k], (uint32_t)a);
+                acc = HI ? __builtin_amdgcn_sad_hi_u8(f, cur[j][k], acc) : __builtin_amdgcn_sad_u8(f, cur[j][k], acc);
+            }
+        }
+        return acc;
+    }
+
+    __device__ __forceinline__ void pair(int x0, int y0, int x1, int y1, uint32_t& c0, uint32_t& c1) const {
+        uint32_t acc = pt<false>(x0, y0, 0u);
+        acc = pt<true>(x1, y1, acc);
+        acc = group_sum<L>(acc);
+        c0 = acc & 0xFFFFu;
+        c1 = acc >> 16;
+    }
+
+    // HCSP at the origin: the centre row is read once (K + 2 words from 4
+    // bytes left of the block), shifted by 2 bytes, and v_qsad_pk_u16_u8
+    // yields the offsets -2, -1, 0, +1 together; the rows above and below are
+    // word aligned.
+    __device__ __forceinline__ void cross0(uint32_t (&c)[7]) const {
+        uint64_t q = 0;
+        uint32_t s2 = 0, s3 = 0;
+        const uint32_t* w = reinterpret_cast<const uint32_t*>(lds + base - 4);
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+            uint32_t d[K + 2], up[K], dn[K];
+#pragma unroll
+            for (int k = 0; k < K + 2; ++k) d[k] = w[j * JW + k];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                up[k] = w[j * JW - WDW + 1 + k];
+                dn[k] = w[j * JW + WDW + 1 + k];
+            }
+            uint32_t f[K + 1];
+#pragma unroll
+            for (int k = 0; k <= K; ++k) f[k] = __builtin_amdgcn_alignbyte(d[k + 1], d[k], 2u);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                q = __builtin_amdgcn_qsad_pk_u16_u8(((uint64_t)f[k + 1] << 32) | f[k], cur[j][k], q);
+                s2 = __builtin_amdgcn_sad_u8(f[k + 1], cur[j][k], s2);    // (+2, 0)
+                s2 = __builtin_amdgcn_sad_hi_u8(up[k], cur[j][k], s2);    // (0, -1)
+                s3 = __builtin_amdgcn_sad_u8(dn[k], cur[j][k], s3);       // (0, +1)
+            }
+        }
+        const uint32_t lo = group_sum<L>((uint32_t)q);          // (-2) | (-1) << 16
+        const uint32_t hi = group_sum<L>((uint32_t)(q >> 32));  // (0) | (+1) << 16
+        s2 = group_sum<L>(s2);
+        s3 = group_sum<L>(s3);
+        c[0] = hi & 0xFFFFu;
+        c[1] = lo >> 16;
+        c[2] = hi >> 16;
+        c[3] = lo & 0xFFFFu;
+        c[4] = s2 & 0xFFFFu;
+        c[5] = s2 >> 16;
+        c[6] = s3;
+    }
+
+    // The cross at any centre (learned start), t = vertical orientation.
+    __device__ __forceinline__ void cross(int cx, int cy, bool t, uint32_t (&c)[7]) const {
+        const int ax = t ? 0 : 1, ay = t ? 1 : 0;  // unit step along the long arm
+        uint32_t u;
+        pair(cx, cy, cx - ax, cy - ay, c[0], c[1]);
+        pair(cx + ax, cy + ay, cx - 2 * ax, cy - 2 * ay, c[2], c[3]);
+        pair(cx + 2 * ax, cy + 2 * ay, cx - ay, cy - ax, c[4], c[5]);
+        pair(cx + ay, cy + ax, cx, cy, c[6], u);
+    }
+
+    __device__ __forceinline__ void diamond(int cx, int cy, bool t, uint32_t (&c)[4]) const {
+        const int ax = t ? 0 : 1, ay = t ? 1 : 0;
+        pair(cx - 2 * ax, cy - 2 * ay, cx + 2 * ax, cy + 2 * ay, c[0], c[1]);
+        pair(cx - ay, cy - ax, cx + ay, cy + ax, c[2], c[3]);
+    }
+
+    __device__ __forceinline__ void mids(int cx, int cy, bool t, uint32_t (&c)[2]) const {
+        const int ax = t ? 0 : 1, ay = t ? 1 : 0;
+        pair(cx - ax, cy - ay, cx + ax, cy + ay, c[0], c[1]);
+    }
+
+    __device__ __forceinline__ void probe(int sx, int sy, uint32_t (&c)[2]) const { pair(0, 0, sx, sy, c[0], c[1]); }
+};
+
+// XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
+// give each XCD a contiguous run of tiles (neighbouring tiles share window
+// rows through that XCD's L2).
+__device__ __forceinline__ int xcd_remap(int i, int n) {
+    const int q = n >> 3, r = n & 7;
+    const int x = i & 7, k = i >> 3;
+    return x * q + min(x, r) + k;
+}
+
+// flags: DCDS_SIMPLIFIED (Step 4 of DCDS^S), DCDS_VEC16 (16-byte loads allowed).
+enum { DCDS_SIMPLIFIED = 1, DCDS_VEC16 = 2 };
+
+template <int B, int RPL, int WPG, int RMAX>
+__global__ __launch_bounds__(64 * WPG) void k_dcds(FrameArgs a, int flags, const int16_t* __restrict__ start,
+                                                    const uint8_t* __restrict__ orient, int16_t* __restrict__ mv,
+                                                    uint32_t* __restrict__ sad, uint32_t* __restrict__ nsp) {
+    using G = DcdsGeo<B, RPL, WPG, RMAX>;
+    constexpr int L = G::L, K = G::K;
+    extern __shared__ uint32_t smem[];
+    const int R = a.R;
+    const int BMW = bitmap_words(R);
+    uint32_t* win = smem;
+    uint32_t* bms = smem + G::WIN_WORDS;
+
+    int t = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = t % a.tiles_x;
+    t /= a.tiles_x;
+    const int ty = t % a.tiles_y;
+    const int pair = t / a.tiles_y;
+    const uint8_t* curf = a.cur + (long long)pair * a.pair_stride;
+    const uint8_t* reff = a.ref + (long long)pair * a.pair_stride;
+    const int X0 = tx * G::TW, Y0 = ty * G::TH;
+
+    const bool vec = (flags & DCDS_VEC16) != 0;
+    if (vec)
+        stage<G::NEED * 4, G::WDW, G::WR, 64 * WPG, true>(win, reff, a.W, a.H, a.pitch, X0 - G::ML, Y0 - G::MR);
+    else
+        stage<G::NEED * 4, G::WDW, G::WR, 64 * WPG, false>(win, reff, a.W, a.H, a.pitch, X0 - G::ML, Y0 - G::MR);
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int b = lane / L, g = lane % L;
+    const int bx = tx * G::BPW + b, by = ty * WPG + wave;
+    const bool exists = bx < a.bw && by < a.bh;
+    uint32_t* bm = bms + (wave * G::BPW + b) * BMW;
+    for (int i = g; i < BMW; i += L) bm[i] = 0u;
+
+    FrameEval<B, RPL, G::WDW> ev;
+    ev.lds = reinterpret_cast<const uint8_t*>(win);
+    ev.base = (G::MR + wave * B + g) * (G::WDW * 4) + G::ML + b * B;
+    const int x0 = bx * B, y0 = by * B;
+    if (exists) {
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+            const uint8_t* row = curf + (size_t)(y0 + g + j * L) * a.pitch + x0;
+            if (K == 4 && vec) {
+                const uint4 v = *reinterpret_cast<const uint4*>(row);
+                ev.cur[j][0] = v.x;
+                ev.cur[j][1] = v.y;
+                ev.cur[j][2] = v.z;
+                ev.cur[j][3] = v.w;
+            } else {
+#pragma unroll
+                for (int k = 0; k < K; ++k) ev.cur[j][k] = reinterpret_cast<const uint32_t*>(row)[k];
+            }
+        }
+    }
+    Roles<L> ro;
+    ro.init(g);
+    __syncthreads();
+    if (!exists) return;
+
+    Bounds bd;
+    bd.lox = max(-R, -x0);
+    bd.hix = min(R, a.W - B - x0);
+    bd.loy = max(-R, -y0);
+    bd.hiy = min(R, a.H - B - y0);
+    const long long idx = ((long long)pair * a.bh + by) * a.bw + bx;
+    const bool seeded = start != nullptr;
+    int sx = 0, sy = 0;
+    bool ov = false;
+    if (seeded) {
+        sx = start[2 * idx];
+        sy = start[2 * idx + 1];
+        ov = orient != nullptr && orient[idx] != 0;
+    }
+    const SearchOut r =
+        dcds_search<L>(ev, R, bd, bm, ro, b * L, (flags & DCDS_SIMPLIFIED) != 0, seeded, sx, sy, ov);
+    if (g == 0) {
+        mv[2 * idx] = (int16_t)r.x;
+        mv[2 * idx + 1] = (int16_t)r.y;
+        sad[idx] = r.cost;
+        nsp[idx] = r.nsp;
+    }
+}
+
+}  // namespace me

@@ -1,15 +1,10 @@
 // Device helpers for block matching on gfx950 (CDNA4, wave64).
 //
-// Data layout used by every kernel:
-//   - a search window is staged in LDS as rows of 32-bit words; word w of a
-//     row holds frame bytes xs + 4w .. xs + 4w + 3 (little endian), with xs a
-//     multiple of 4, so any byte column is reached with two aligned LDS words
-//     and one v_alignbyte_b32;
-//   - a B x B current block is spread over B lanes, one row per lane, the row
-//     held in B/4 VGPRs;
-//   - SAD of a candidate = per-lane v_sad_u8 chain over the row, then a sum
-//     over the block's B lanes with DPP row operations (the B lanes of a block
-//     never straddle a 16-lane DPP row).
+// Data layout used by every kernel: a search window is staged in LDS as rows
+// of 32-bit words; word w of a row holds frame bytes xs + 4w .. xs + 4w + 3
+// (little endian), with xs a multiple of 4, so any byte column is reached
+// with two aligned LDS words and one v_alignbyte_b32.  Sums over the lanes of
+// one block use DPP (the lanes of a block never straddle a 16-lane DPP row).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -31,7 +26,7 @@ __device__ __forceinline__ uint32_t dpp(uint32_t x) {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xf, 0xf, false);
 }
 
-// Sum over aligned groups of L lanes (L = 8 or 16); every lane of the group
+// Sum over aligned groups of L lanes (L = 4, 8 or 16); every lane of the group
 // receives the total.  Packed 2 x u16 sums add without carries as long as each
 // half's total stays below 2^16.
 template <int L>
@@ -43,6 +38,13 @@ __device__ __forceinline__ uint32_t group_sum<16>(uint32_t x) {
     x += dpp<DPP_ROR4>(x);
     x += dpp<DPP_ROR2>(x);
     x += dpp<DPP_ROR1>(x);
+    return x;
+}
+
+template <>
+__device__ __forceinline__ uint32_t group_sum<4>(uint32_t x) {
+    x += dpp<DPP_QUAD_XOR1>(x);
+    x += dpp<DPP_QUAD_XOR2>(x);
     return x;
 }
 
@@ -64,37 +66,6 @@ __device__ __forceinline__ uint32_t group_min<16>(uint32_t x) {
     x = min(x, dpp<DPP_ROR2>(x));
     x = min(x, dpp<DPP_ROR1>(x));
     return x;
-}
-
-// Byte SAD of one row of B pixels: the reference row starts at byte `col` of
-// LDS row `row` (words), the current row is in cur[0 .. B/4).  The result is
-// added to acc (low half).
-template <int B>
-__device__ __forceinline__ uint32_t row_sad_lo(const uint32_t* row, int col, const uint32_t (&cur)[B / 4],
-                                               uint32_t acc) {
-    const uint32_t* p = row + (col >> 2);
-    const uint32_t s = (uint32_t)(col & 3);
-    uint32_t d[B / 4 + 1];
-#pragma unroll
-    for (int k = 0; k <= B / 4; ++k) d[k] = p[k];
-#pragma unroll
-    for (int k = 0; k < B / 4; ++k) acc = __builtin_amdgcn_sad_u8(__builtin_amdgcn_alignbyte(d[k + 1], d[k], s), cur[k], acc);
-    return acc;
-}
-
-// Same, accumulated into the high 16 bits (v_sad_hi_u8).
-template <int B>
-__device__ __forceinline__ uint32_t row_sad_hi(const uint32_t* row, int col, const uint32_t (&cur)[B / 4],
-                                               uint32_t acc) {
-    const uint32_t* p = row + (col >> 2);
-    const uint32_t s = (uint32_t)(col & 3);
-    uint32_t d[B / 4 + 1];
-#pragma unroll
-    for (int k = 0; k <= B / 4; ++k) d[k] = p[k];
-#pragma unroll
-    for (int k = 0; k < B / 4; ++k)
-        acc = __builtin_amdgcn_sad_hi_u8(__builtin_amdgcn_alignbyte(d[k + 1], d[k], s), cur[k], acc);
-    return acc;
 }
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }

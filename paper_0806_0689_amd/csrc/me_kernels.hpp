@@ -1,19 +1,9 @@
-// FS and DCDS kernels over frame pairs, and DCDS over cost surfaces.
+// Full search over frame pairs, and DCDS over cost surfaces.
 #pragma once
 
-#include "me_search.hpp"
+#include "me_dcds.hpp"
 
 namespace me {
-
-struct FrameArgs {
-    const uint8_t* cur;
-    const uint8_t* ref;
-    long long pair_stride;  // bytes between consecutive pairs
-    int W, H, pitch;
-    int R;
-    int bw, bh;             // blocks per row / column
-    int tiles_x, tiles_y;   // DCDS tiles per row / column
-};
 
 // Copies rows [ys, ys + rows) x words [xs/4, xs/4 + words) of a frame into
 // LDS; words outside the frame read as 0 (no valid candidate ever uses them).
@@ -32,146 +22,70 @@ __device__ __forceinline__ void stage_window(uint32_t* dst, const uint8_t* frame
 }
 
 // ---------------------------------------------------------------------------
-// DCDS over frames.  A workgroup of WPG waves owns a tile of BPW x WPG blocks
-// (BPW = 64 / B blocks side by side per wave, B lanes per block, one row per
-// lane).  The tile's window, widened by the range on every side, is staged in
-// LDS once; each block keeps its visited-point bitmap in LDS too.
-// ---------------------------------------------------------------------------
-template <int B>
-struct FrameEval {
-    const uint32_t* win;
-    int WD;       // words per LDS row
-    int rowbase;  // LDS row of this lane's current-block row at y offset 0
-    int colbase;  // LDS byte column of the block's left edge at x offset 0
-    uint32_t cur[B / 4];
-
-    template <int N>
-    __device__ __forceinline__ void operator()(const int (&x)[N], const int (&y)[N], uint32_t (&c)[N]) const {
-#pragma unroll
-        for (int i = 0; i < N; i += 2) {
-            uint32_t acc = row_sad_lo<B>(win + (rowbase + y[i]) * WD, colbase + x[i], cur, 0u);
-            if (i + 1 < N) acc = row_sad_hi<B>(win + (rowbase + y[i + 1]) * WD, colbase + x[i + 1], cur, acc);
-            acc = group_sum<B>(acc);
-            c[i] = acc & 0xFFFFu;
-            if (i + 1 < N) c[i + 1] = acc >> 16;
-        }
-    }
-};
-
-__host__ __device__ constexpr int dcds_window_words(int tile_w, int R) { return tile_w / 4 + 2 * margin_words(R) + 1; }
-__host__ __device__ constexpr int bitmap_words(int R) { return ((2 * R + 1) * (2 * R + 1) + 31) / 32; }
-
-template <int B, int WPG>
-__host__ __device__ constexpr size_t dcds_lds_bytes(int R) {
-    return (size_t)4 * ((WPG * B + 2 * R) * dcds_window_words((64 / B) * B, R) + (64 / B) * WPG * bitmap_words(R));
-}
-
-template <int B, int WPG, int ALGO>
-__global__ __launch_bounds__(64 * WPG) void k_dcds(FrameArgs a, const int16_t* __restrict__ start,
-                                                    const uint8_t* __restrict__ orient, int16_t* __restrict__ mv,
-                                                    uint32_t* __restrict__ sad, uint32_t* __restrict__ nsp) {
-    constexpr int L = B, BPW = 64 / B, TW = BPW * B, TH = WPG * B;
-    extern __shared__ uint32_t smem[];
-    const int R = a.R;
-    const int MW = margin_words(R);
-    const int WD = dcds_window_words(TW, R);
-    const int WR = TH + 2 * R;
-    const int BMW = bitmap_words(R);
-    uint32_t* win = smem;
-    uint32_t* bms = smem + WR * WD;
-
-    int t = blockIdx.x;
-    const int tx = t % a.tiles_x;
-    t /= a.tiles_x;
-    const int ty = t % a.tiles_y;
-    const int pair = t / a.tiles_y;
-    const uint8_t* curf = a.cur + (long long)pair * a.pair_stride;
-    const uint8_t* reff = a.ref + (long long)pair * a.pair_stride;
-    const int X0 = tx * TW, Y0 = ty * TH;
-
-    stage_window(win, reff, a.W, a.H, a.pitch, X0 - 4 * MW, Y0 - R, WR, WD, threadIdx.x, 64 * WPG);
-
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int b = lane / L, v = lane % L;
-    const int bx = tx * BPW + b, by = ty * WPG + wave;
-    const bool exists = bx < a.bw && by < a.bh;
-    uint32_t* bm = bms + (wave * BPW + b) * BMW;
-    for (int i = v; i < BMW; i += L) bm[i] = 0u;
-
-    FrameEval<B> ev;
-    ev.win = win;
-    ev.WD = WD;
-    ev.rowbase = wave * B + v + R;
-    ev.colbase = b * B + 4 * MW;
-    const int x0 = bx * B, y0 = by * B;
-    if (exists) {
-        const uint32_t* crow = reinterpret_cast<const uint32_t*>(curf + (size_t)(y0 + v) * a.pitch + x0);
-#pragma unroll
-        for (int k = 0; k < B / 4; ++k) ev.cur[k] = crow[k];
-    }
-    __syncthreads();
-    if (!exists) return;
-
-    Bounds bd;
-    bd.lox = max(-R, -x0);
-    bd.hix = min(R, a.W - B - x0);
-    bd.loy = max(-R, -y0);
-    bd.hiy = min(R, a.H - B - y0);
-    const long long idx = ((long long)pair * a.bh + by) * a.bw + bx;
-    const bool has_start = start != nullptr;
-    int sx = 0, sy = 0;
-    bool ov = false;
-    if (has_start) {
-        sx = start[2 * idx];
-        sy = start[2 * idx + 1];
-        ov = orient != nullptr && orient[idx] != 0;
-    }
-    const SearchOut r = dcds_search<L, ALGO>(ev, R, bd, bm, v, b * L, has_start, sx, sy, ov);
-    if (v == 0) {
-        mv[2 * idx] = (int16_t)r.x;
-        mv[2 * idx + 1] = (int16_t)r.y;
-        sad[idx] = r.cost;
-        nsp[idx] = r.nsp;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// DCDS over cost surfaces (ideal-condition analysis).  16 lanes per surface;
-// the "distortion" of a point is read from the caller's table.
+// DCDS over cost surfaces (ideal-condition analysis of §III-C).  16 lanes per
+// surface; the "distortion" of a point is read from the caller's table.
+// Points outside the window are clamped to it for the read (they are masked).
 // ---------------------------------------------------------------------------
 struct SurfaceEval {
     const int32_t* cost;
     int R;
-    template <int N>
-    __device__ __forceinline__ void operator()(const int (&x)[N], const int (&y)[N], uint32_t (&c)[N]) const {
-#pragma unroll
-        for (int i = 0; i < N; ++i) c[i] = (uint32_t)cost[(y[i] + R) * (2 * R + 1) + (x[i] + R)];
+    __device__ __forceinline__ uint32_t at(int x, int y) const {
+        x = clampi(x, -R, R);
+        y = clampi(y, -R, R);
+        return (uint32_t)cost[(y + R) * (2 * R + 1) + (x + R)];
+    }
+    __device__ __forceinline__ void cross(int cx, int cy, bool t, uint32_t (&c)[7]) const {
+        const int ax = t ? 0 : 1, ay = t ? 1 : 0;
+        c[0] = at(cx, cy);
+        c[1] = at(cx - ax, cy - ay);
+        c[2] = at(cx + ax, cy + ay);
+        c[3] = at(cx - 2 * ax, cy - 2 * ay);
+        c[4] = at(cx + 2 * ax, cy + 2 * ay);
+        c[5] = at(cx - ay, cy - ax);
+        c[6] = at(cx + ay, cy + ax);
+    }
+    __device__ __forceinline__ void cross0(uint32_t (&c)[7]) const { cross(0, 0, false, c); }
+    __device__ __forceinline__ void diamond(int cx, int cy, bool t, uint32_t (&c)[4]) const {
+        const int ax = t ? 0 : 1, ay = t ? 1 : 0;
+        c[0] = at(cx - 2 * ax, cy - 2 * ay);
+        c[1] = at(cx + 2 * ax, cy + 2 * ay);
+        c[2] = at(cx - ay, cy - ax);
+        c[3] = at(cx + ay, cy + ax);
+    }
+    __device__ __forceinline__ void mids(int cx, int cy, bool t, uint32_t (&c)[2]) const {
+        const int ax = t ? 0 : 1, ay = t ? 1 : 0;
+        c[0] = at(cx - ax, cy - ay);
+        c[1] = at(cx + ax, cy + ay);
+    }
+    __device__ __forceinline__ void probe(int sx, int sy, uint32_t (&c)[2]) const {
+        c[0] = at(0, 0);
+        c[1] = at(sx, sy);
     }
 };
 
-template <int ALGO>
 __global__ __launch_bounds__(256) void k_dcds_surface(const int32_t* __restrict__ cost, const uint8_t* __restrict__ valid,
-                                                      int n, int R, const int16_t* __restrict__ start,
+                                                      int n, int R, bool simplified, const int16_t* __restrict__ start,
                                                       const uint8_t* __restrict__ orient, int16_t* __restrict__ mv,
                                                       uint32_t* __restrict__ out_cost, uint32_t* __restrict__ nsp) {
     constexpr int L = 16;
     extern __shared__ uint32_t smem[];
     const int BMW = bitmap_words(R);
-    const int g = threadIdx.x / L, v = threadIdx.x % L;
-    const long long s = (long long)blockIdx.x * (256 / L) + g;
-    uint32_t* bm = smem + g * BMW;
-    for (int i = v; i < BMW; i += L) bm[i] = 0u;
+    const int gi = threadIdx.x / L, g = threadIdx.x % L;
+    const long long s = (long long)blockIdx.x * (256 / L) + gi;
+    uint32_t* bm = smem + gi * BMW;
+    for (int i = g; i < BMW; i += L) bm[i] = 0u;
+    Roles<L> ro;
+    ro.init(g);
     __syncthreads();
     if (s >= n) return;
     const int side = 2 * R + 1;
     SurfaceEval ev{cost + s * side * side, R};
-    // The candidate set is the bounding box of the valid mask (the frame case
-    // always yields a rectangle).
+    // The candidate set is the bounding box of the valid mask, plus the origin.
     Bounds bd{-R, R, -R, R};
     if (valid) {
         const uint8_t* vm = valid + s * side * side;
         int lox = R + 1, hix = -R - 1, loy = R + 1, hiy = -R - 1;
-        for (int i = v; i < side * side; i += L) {
+        for (int i = g; i < side * side; i += L) {
             if (vm[i]) {
                 const int yy = i / side - R, xx = i % side - R;
                 lox = min(lox, xx);
@@ -186,17 +100,17 @@ __global__ __launch_bounds__(256) void k_dcds_surface(const int32_t* __restrict_
         bd.loy = min(0, (int)group_min<16>((uint32_t)(loy + 64)) - 64);
         bd.hiy = max(0, 64 - (int)group_min<16>((uint32_t)(64 - hiy)));
     }
-    const bool has_start = start != nullptr;
+    const bool seeded = start != nullptr;
     int sx = 0, sy = 0;
     bool ov = false;
-    if (has_start) {
+    if (seeded) {
         sx = start[2 * s];
         sy = start[2 * s + 1];
         ov = orient != nullptr && orient[s] != 0;
     }
     const int lane = threadIdx.x & 63;
-    const SearchOut r = dcds_search<L, ALGO>(ev, R, bd, bm, v, (lane / L) * L, has_start, sx, sy, ov);
-    if (v == 0) {
+    const SearchOut r = dcds_search<L>(ev, R, bd, bm, ro, (lane / L) * L, simplified, seeded, sx, sy, ov);
+    if (g == 0) {
         mv[2 * s] = (int16_t)r.x;
         mv[2 * s + 1] = (int16_t)r.y;
         out_cost[s] = r.cost;

@@ -108,3 +108,19 @@ def test_product_path_does_not_import_the_oracle():
             text = open(os.path.join(ROOT, "oracle", fn)).read()
             assert not re.search(r"^\s*(import|from)\s+paper_0806_0689_amd\b", text, re.M), fn
             assert '#include "me' not in text and "csrc" not in text, fn
+
+
+def test_config_set_get_and_checks():
+    d16 = me.me_get_config(16, 15)
+    assert me.me_set_config(16, 15, (4, 2)) == me.ME_OK
+    assert me.me_get_config(16, 15) == (4, 2)
+    assert me.me_get_config(16, 9) == (4, 2)       # same range class 8..15
+    assert me.me_get_config(16, 7) == me.me_get_config(16, 1)
+    assert me.me_set_config(16, 15, None) == me.ME_OK
+    assert me.me_get_config(16, 15) == d16
+    assert me.me_set_config(8, 15, (4, 2)) == me.ME_EUNSUPPORTED   # 8x8 blocks: 1 or 2 rows per lane
+    assert me.me_set_config(16, 15, (3, 2)) == me.ME_EUNSUPPORTED
+    assert me.me_set_config(16, 15, (2, 8)) == me.ME_EUNSUPPORTED
+    assert me.me_set_config(12, 15, (2, 2)) == me.ME_EUNSUPPORTED
+    assert me.me_set_config(16, 0, (2, 2)) == me.ME_EUNSUPPORTED
+    assert me.lib().me_get_config(16, 15, None) == me.ME_EINVAL

@@ -211,3 +211,30 @@ def test_random_surfaces_vs_oracle(R):
                 kw = dict(start=start[i], orient_v=bool(orient[i])) if seeded else {}
                 emv, ec, en = oracle.dcds_surface(cost[i], valid[i], variant=variant, **kw)
                 assert (tuple(gmv[i]), gc[i], gn[i]) == (emv, ec, en), (R, algo, seeded, i)
+
+
+CONFIGS16 = [(r, w) for r in (1, 2, 4) for w in (1, 2, 4)]
+CONFIGS8 = [(r, w) for r in (1, 2) for w in (1, 2, 4)]
+
+
+@pytest.mark.parametrize("B,cfg", [(16, c) for c in CONFIGS16] + [(8, c) for c in CONFIGS8])
+def test_every_kernel_configuration(B, cfg, seq1080):
+    """Each rows-per-lane x waves-per-group layout gives the oracle's results:
+    ragged small frames at every range class, and two 1920x1088 pairs."""
+    try:
+        for R in (3, 7, 8, 15, 16, 31):
+            assert me.me_set_config(B, R, cfg) == me.ME_OK
+            cur, ref = random_pair(48, 80, B, min(R, 7), seed=R * 11 + B)
+            say("case config", cfg, "B=%d R=%d ragged" % (B, R))
+            tc, tr = to_dev(cur[None]), to_dev(ref[None])
+            assert_same(me.dcds(tc, tr, B, R), oracle_pairs(oracle.dcds, cur[None], ref[None], B, R), "cfg dcds")
+            assert_same(me.dcds(tc, tr, B, R, algo=me.ME_ALGO_DCDS_S),
+                        oracle_pairs(oracle.dcds, cur[None], ref[None], B, R, variant=oracle.VARIANT_DCDS_S),
+                        "cfg dcds_s")
+        tseq = to_dev(seq1080[:3])
+        say("case config", cfg, "B=%d 1080p" % B)
+        assert_same(me.dcds(tseq[1:], tseq[:-1], B, 15),
+                    oracle_pairs(oracle.dcds, seq1080[1:3], seq1080[:2], B, 15), "cfg 1080p")
+    finally:
+        for R in (7, 15, 31):
+            me.me_set_config(B, R, None)
