@@ -127,7 +127,8 @@ def main():
     if args.calib_copy:
         src = torch.ones(256 << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        dst.copy_(src)                 # runtime copy kernel: reads and writes 256 MiB
+        torch.add(src, 1, out=dst)     # elementwise kernel: reads and writes 256 MiB
         torch.cuda.synchronize()
         del src, dst
 
