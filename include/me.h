@@ -144,6 +144,56 @@ int me_dcds_surface(const int32_t *cost, const uint8_t *valid, int32_t n, int32_
                     const me_mv *start, const uint8_t *orient,
                     me_mv *mv, uint32_t *cost_out, uint32_t *nsp, void *stream);
 
+/*
+ * Batched search over many sequences in one persistent launch (this
+ * library's addition; the search itself is the one above).  A job is one
+ * frame sequence (its own size, pitch and pair count; the block size and the
+ * range are the batch's).  Each job's arguments follow me_fullsearch /
+ * me_dcds_ex; start/orient must be NULL for ME_ALGO_FS.  Up to 4096 jobs.
+ *
+ * The host copies the job table into a pinned buffer; the device work is
+ * {table copy, counter reset, persistent kernel}, captured once per kernel
+ * variant into a hipGraph and replayed on `stream`, so sizes may change from
+ * call to call without re-capture.  Two internal slots alternate: a call waits
+ * (on the host) for the call two before it to finish before reusing its slot.
+ * Results equal me_fullsearch / me_dcds_ex on each job.  One device per
+ * process (ME_EUNSUPPORTED if the current device changes).
+ */
+typedef struct {
+    const uint8_t *cur, *ref;
+    int32_t width, height, pitch, n_pairs;
+    int64_t pair_stride;
+    me_mv *mv;
+    uint32_t *sad, *nsp;
+    const me_mv *start;    /* optional (DCDS only) */
+    const uint8_t *orient; /* optional (DCDS only; needs start) */
+} me_job;
+
+int me_batch(const me_job *jobs, int32_t n_jobs, int32_t algo, int32_t block, int32_t range, void *stream);
+
+/*
+ * Autotuner: times every DCDS kernel configuration (me_config) on the given
+ * batch with `reps` launches each (me_batch on `stream`, synchronising it),
+ * keeps the fastest for (block, range class) via me_set_config, and returns it
+ * with its time per launch in milliseconds (best, best_ms may be NULL).
+ * algo: ME_ALGO_DCDS or ME_ALGO_DCDS_S.  Outputs of the jobs are overwritten.
+ *
+ * me_autotune_save writes every result of this process (and every entry
+ * loaded) as a text file keyed by GPU architecture and HIP runtime version.
+ * me_autotune_load applies the entries that match the current device and
+ * runtime; malformed lines are skipped and counted in *rejected, entries for
+ * other hardware are ignored.  ME_EINVAL if the file cannot be opened (the
+ * built-in defaults then stay in force).
+ */
+int me_autotune(const me_job *jobs, int32_t n_jobs, int32_t algo, int32_t block, int32_t range, int32_t reps,
+                me_config *best, float *best_ms, void *stream);
+int me_autotune_save(const char *path);
+int me_autotune_load(const char *path, int32_t *applied, int32_t *rejected);
+
+/* Releases the library's device and pinned buffers, graphs and streams (no
+ * batch may be in flight).  Later calls allocate them again.               */
+int me_shutdown(void);
+
 #ifdef __cplusplus
 }
 #endif

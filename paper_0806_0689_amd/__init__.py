@@ -36,11 +36,28 @@ EXPORTS = [
     "me_dcds",
     "me_dcds_ex",
     "me_dcds_surface",
+    "me_batch",
+    "me_autotune",
+    "me_autotune_save",
+    "me_autotune_load",
+    "me_shutdown",
 ]
+
+MAX_JOBS = 4096
 
 
 class MeConfig(ctypes.Structure):
     _fields_ = [("rows_per_lane", ctypes.c_int32), ("waves_per_group", ctypes.c_int32)]
+
+
+class MeJob(ctypes.Structure):
+    _fields_ = [
+        ("cur", ctypes.c_void_p), ("ref", ctypes.c_void_p),
+        ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("pitch", ctypes.c_int32), ("n_pairs", ctypes.c_int32),
+        ("pair_stride", ctypes.c_int64),
+        ("mv", ctypes.c_void_p), ("sad", ctypes.c_void_p), ("nsp", ctypes.c_void_p),
+        ("start", ctypes.c_void_p), ("orient", ctypes.c_void_p),
+    ]
 
 
 class MEError(RuntimeError):
@@ -75,6 +92,17 @@ def lib() -> ctypes.CDLL:
         L.me_set_config.restype = ctypes.c_int
         L.me_get_config.argtypes = [i32, i32, ctypes.POINTER(MeConfig)]
         L.me_get_config.restype = ctypes.c_int
+        L.me_batch.argtypes = [ctypes.POINTER(MeJob), i32, i32, i32, i32, vp]
+        L.me_batch.restype = ctypes.c_int
+        L.me_autotune.argtypes = [ctypes.POINTER(MeJob), i32, i32, i32, i32, i32, ctypes.POINTER(MeConfig),
+                                  ctypes.POINTER(ctypes.c_float), vp]
+        L.me_autotune.restype = ctypes.c_int
+        L.me_autotune_save.argtypes = [ctypes.c_char_p]
+        L.me_autotune_save.restype = ctypes.c_int
+        L.me_autotune_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.me_autotune_load.restype = ctypes.c_int
+        L.me_shutdown.argtypes = []
+        L.me_shutdown.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -116,6 +144,34 @@ def me_get_config(block, range_):
     rc = lib().me_get_config(block, range_, ctypes.byref(c))
     _check(rc, "me_get_config")
     return c.rows_per_lane, c.waves_per_group
+
+
+def me_batch(jobs, n_jobs, algo, block, range_, stream=0):
+    """jobs: a ctypes array of MeJob (or None)."""
+    return lib().me_batch(jobs, n_jobs, algo, block, range_, stream)
+
+
+def me_autotune(jobs, n_jobs, algo, block, range_, reps, stream=0):
+    """Returns (status, (rows_per_lane, waves_per_group), ms)."""
+    best = MeConfig()
+    ms = ctypes.c_float(0.0)
+    rc = lib().me_autotune(jobs, n_jobs, algo, block, range_, reps, ctypes.byref(best), ctypes.byref(ms), stream)
+    return rc, (best.rows_per_lane, best.waves_per_group), ms.value
+
+
+def me_autotune_save(path):
+    return lib().me_autotune_save(os.fsencode(path))
+
+
+def me_autotune_load(path):
+    """Returns (status, applied, rejected)."""
+    a, r = ctypes.c_int32(0), ctypes.c_int32(0)
+    rc = lib().me_autotune_load(os.fsencode(path), ctypes.byref(a), ctypes.byref(r))
+    return rc, a.value, r.value
+
+
+def me_shutdown():
+    return lib().me_shutdown()
 
 
 def set_config(block, range_, cfg):
@@ -201,6 +257,39 @@ def dcds(cur, ref, block=16, range_=7, algo=ME_ALGO_DCDS, start=None, orient=Non
                     mv.data_ptr(), sad.data_ptr(), nsp.data_ptr(), _stream(stream))
     _check(rc, "me_dcds_ex")
     return mv, sad, nsp
+
+
+def make_jobs(pairs, block, starts=None, orients=None, outs=None):
+    """Job table for me_batch from a list of (cur, ref) tensor pairs ([H, W] or
+    [P, H, W]); allocates outputs unless given.  Returns (ctypes array, outputs)."""
+    jobs = (MeJob * max(1, len(pairs)))()
+    outputs = []
+    for i, (cur, ref) in enumerate(pairs):
+        P, H, W, pitch, stride = _frames(cur, ref)
+        o = outs[i] if outs is not None else _outputs(P, H // block, W // block, cur.device, None)
+        mv, sad, nsp = o
+        st = starts[i] if starts is not None else None
+        orr = orients[i] if orients is not None else None
+        jobs[i] = MeJob(cur.data_ptr(), ref.data_ptr(), W, H, pitch, P, stride, mv.data_ptr(), sad.data_ptr(),
+                        nsp.data_ptr(), st.data_ptr() if st is not None else None,
+                        orr.data_ptr() if orr is not None else None)
+        outputs.append(o)
+    return jobs, outputs
+
+
+def batch(pairs, block=16, range_=15, algo=ME_ALGO_DCDS, starts=None, orients=None, outs=None, stream=None):
+    """One persistent launch over many sequences; returns one (mv, sad, nsp) per job."""
+    jobs, outputs = make_jobs(pairs, block, starts, orients, outs)
+    _check(me_batch(jobs, len(pairs), algo, block, range_, _stream(stream)), "me_batch")
+    return outputs
+
+
+def autotune(pairs, block=16, range_=15, algo=ME_ALGO_DCDS, reps=5, stream=None):
+    """Times every DCDS configuration on this batch and keeps the fastest."""
+    jobs, outputs = make_jobs(pairs, block)
+    rc, cfg, ms = me_autotune(jobs, len(pairs), algo, block, range_, reps, _stream(stream))
+    _check(rc, "me_autotune")
+    return cfg, ms
 
 
 def dcds_surface(cost, valid=None, algo=ME_ALGO_DCDS, start=None, orient=None, stream=None):

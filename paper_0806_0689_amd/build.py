@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libme.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["me_api.hip"]
+SOURCES = ["me_api.hip", "me_batch.hip"]
 FLAGS = [
     "--offload-arch=gfx950",
     "-O3",
@@ -20,6 +20,7 @@ FLAGS = [
     # Packed FP32 instructions stay off in every device build.
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
+    "-fvisibility=hidden",
 ]
 
 

@@ -6,11 +6,15 @@
 #include <atomic>
 
 #include "me.h"
+#include "me_host.hpp"
 #include "me_kernels.hpp"
+#include "me_surface.hpp"
 
 using namespace me;
+using namespace me::host;
 
-namespace {
+namespace me {
+namespace host {
 
 bool aligned(const void* p, uintptr_t m) { return ((uintptr_t)p & (m - 1)) == 0; }
 
@@ -48,8 +52,6 @@ FrameArgs frame_args(const uint8_t* cur, const uint8_t* ref, int32_t width, int3
 
 int launched() { return hipGetLastError() == hipSuccess ? ME_OK : ME_EDEVICE; }
 
-constexpr size_t kMaxLds = 160 * 1024;  // LDS per compute unit on gfx950
-
 // ---------------------------------------------------------------------------
 // DCDS kernel configurations: rows per lane x waves per workgroup, per block
 // size and range class.  Defaults come from measurements on MI355X; the
@@ -62,14 +64,28 @@ int default_cfg(int block, int rc) {
     (void)rc;
     return block == 16 ? (2 * 16 + 4) : (2 * 16 + 4);
 }
-int current_cfg(int block, int rc) {
-    const int v = g_cfg[block == 16][rc].load(std::memory_order_relaxed);
-    return v ? v : default_cfg(block, rc);
+void current_cfg(int block, int rc, int* rpl, int* wpg) {
+    int v = g_cfg[block == 16][rc].load(std::memory_order_relaxed);
+    if (!v) v = default_cfg(block, rc);
+    *rpl = v / 16;
+    *wpg = v % 16;
 }
 bool valid_cfg(int block, int rpl, int wpg) {
     const bool r_ok = block == 16 ? (rpl == 1 || rpl == 2 || rpl == 4) : (rpl == 1 || rpl == 2);
     return r_ok && (wpg == 1 || wpg == 2 || wpg == 4);
 }
+int dcds_flags(int32_t algo, const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t pitch,
+               int64_t pair_stride) {
+    int flags = algo == ME_ALGO_DCDS_S ? DCDS_SIMPLIFIED : 0;
+    if (aligned(cur, 16) && aligned(ref, 16) && (pitch % 16) == 0 && (width % 16) == 0 && (pair_stride % 16) == 0)
+        flags |= DCDS_VEC16;
+    return flags;
+}
+
+}  // namespace host
+}  // namespace me
+
+namespace {
 
 template <int B, int RPL, int WPG, int RMAX>
 int launch_dcds_cfg(const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t height, int32_t pitch,
@@ -135,9 +151,7 @@ int launch_dcds(int32_t block, int rpl, int wpg, const uint8_t* cur, const uint8
 
 }  // namespace
 
-extern "C" {
-
-const char* me_status_string(int status) {
+ME_EXPORT const char* me_status_string(int status) {
     switch (status) {
         case ME_OK: return "ok";
         case ME_EINVAL: return "invalid argument (NULL pointer, size, alignment or pitch)";
@@ -148,7 +162,7 @@ const char* me_status_string(int status) {
     }
 }
 
-int me_set_config(int32_t block, int32_t range, const me_config* cfg) {
+ME_EXPORT int me_set_config(int32_t block, int32_t range, const me_config* cfg) {
     if (block != 8 && block != 16) return ME_EUNSUPPORTED;
     if (range < 1 || range > 31) return ME_EUNSUPPORTED;
     const int rc = range_class(range);
@@ -161,19 +175,20 @@ int me_set_config(int32_t block, int32_t range, const me_config* cfg) {
     return ME_OK;
 }
 
-int me_get_config(int32_t block, int32_t range, me_config* cfg) {
+ME_EXPORT int me_get_config(int32_t block, int32_t range, me_config* cfg) {
     if (!cfg) return ME_EINVAL;
     if (block != 8 && block != 16) return ME_EUNSUPPORTED;
     if (range < 1 || range > 31) return ME_EUNSUPPORTED;
-    const int v = current_cfg(block, range_class(range));
-    cfg->rows_per_lane = v / 16;
-    cfg->waves_per_group = v % 16;
+    int rpl, wpg;
+    current_cfg(block, range_class(range), &rpl, &wpg);
+    cfg->rows_per_lane = rpl;
+    cfg->waves_per_group = wpg;
     return ME_OK;
 }
 
-int me_fullsearch(const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t height, int32_t pitch,
-                  int64_t pair_stride, int32_t n_pairs, int32_t block, int32_t range, me_mv* mv, uint32_t* sad,
-                  uint32_t* nsp, void* stream) {
+ME_EXPORT int me_fullsearch(const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t height, int32_t pitch,
+                            int64_t pair_stride, int32_t n_pairs, int32_t block, int32_t range, me_mv* mv,
+                            uint32_t* sad, uint32_t* nsp, void* stream) {
     int rc = check_frames(cur, ref, width, height, pitch, pair_stride, n_pairs, block, range, mv, sad, nsp);
     if (rc != ME_OK || n_pairs == 0) return rc;
     const FrameArgs a = frame_args(cur, ref, width, height, pitch, pair_stride, block, range, 1, 1);
@@ -188,32 +203,32 @@ int me_fullsearch(const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t
     return launched();
 }
 
-int me_dcds_ex(const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t height, int32_t pitch,
-               int64_t pair_stride, int32_t n_pairs, int32_t block, int32_t range, int32_t algo,
-               const me_mv* start, const uint8_t* orient, me_mv* mv, uint32_t* sad, uint32_t* nsp, void* stream) {
+ME_EXPORT int me_dcds_ex(const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t height, int32_t pitch,
+                         int64_t pair_stride, int32_t n_pairs, int32_t block, int32_t range, int32_t algo,
+                         const me_mv* start, const uint8_t* orient, me_mv* mv, uint32_t* sad, uint32_t* nsp,
+                         void* stream) {
     int rc = check_frames(cur, ref, width, height, pitch, pair_stride, n_pairs, block, range, mv, sad, nsp);
     if (rc != ME_OK) return rc;
     if (algo != ME_ALGO_DCDS && algo != ME_ALGO_DCDS_S) return ME_EUNSUPPORTED;
     if (orient && !start) return ME_EINVAL;
     if (n_pairs == 0) return ME_OK;
-    int flags = algo == ME_ALGO_DCDS_S ? DCDS_SIMPLIFIED : 0;
-    if (aligned(cur, 16) && aligned(ref, 16) && (pitch % 16) == 0 && (width % 16) == 0 && (pair_stride % 16) == 0)
-        flags |= DCDS_VEC16;
-    const int cfg = current_cfg(block, range_class(range));
-    return launch_dcds(block, cfg / 16, cfg % 16, cur, ref, width, height, pitch, pair_stride, n_pairs, range, flags,
-                       start, orient, mv, sad, nsp, reinterpret_cast<hipStream_t>(stream));
+    const int flags = dcds_flags(algo, cur, ref, width, pitch, pair_stride);
+    int rpl, wpg;
+    current_cfg(block, range_class(range), &rpl, &wpg);
+    return launch_dcds(block, rpl, wpg, cur, ref, width, height, pitch, pair_stride, n_pairs, range, flags, start,
+                       orient, mv, sad, nsp, reinterpret_cast<hipStream_t>(stream));
 }
 
-int me_dcds(const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t height, int32_t pitch,
-            int64_t pair_stride, int32_t n_pairs, int32_t block, int32_t range, me_mv* mv, uint32_t* sad,
-            uint32_t* nsp, void* stream) {
+ME_EXPORT int me_dcds(const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t height, int32_t pitch,
+                      int64_t pair_stride, int32_t n_pairs, int32_t block, int32_t range, me_mv* mv, uint32_t* sad,
+                      uint32_t* nsp, void* stream) {
     return me_dcds_ex(cur, ref, width, height, pitch, pair_stride, n_pairs, block, range, ME_ALGO_DCDS, nullptr,
                       nullptr, mv, sad, nsp, stream);
 }
 
-int me_dcds_surface(const int32_t* cost, const uint8_t* valid, int32_t n, int32_t range, int32_t algo,
-                    const me_mv* start, const uint8_t* orient, me_mv* mv, uint32_t* cost_out, uint32_t* nsp,
-                    void* stream) {
+ME_EXPORT int me_dcds_surface(const int32_t* cost, const uint8_t* valid, int32_t n, int32_t range, int32_t algo,
+                              const me_mv* start, const uint8_t* orient, me_mv* mv, uint32_t* cost_out,
+                              uint32_t* nsp, void* stream) {
     if (n < 0) return ME_EINVAL;
     if (range < 1 || range > 31) return ME_EUNSUPPORTED;
     if (algo != ME_ALGO_DCDS && algo != ME_ALGO_DCDS_S) return ME_EUNSUPPORTED;
@@ -227,5 +242,3 @@ int me_dcds_surface(const int32_t* cost, const uint8_t* valid, int32_t n, int32_
                        reinterpret_cast<int16_t*>(mv), cost_out, nsp);
     return launched();
 }
-
-}  // extern "C"

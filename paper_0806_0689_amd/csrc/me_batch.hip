@@ -1,0 +1,410 @@
+// Batched persistent launches (me_batch), the configuration autotuner
+// (me_autotune, me_autotune_save, me_autotune_load) and me_shutdown.
+//
+// A batch is a table of jobs (one frame sequence each, any size).  The table
+// travels through a pinned host buffer into device memory, a tiny kernel
+// resets the tile counter, and one persistent kernel drains all tiles.  The
+// three steps are captured once per kernel variant into a hipGraph and
+// replayed; sizes change through the table, not the graph.  Two slots (pinned
+// buffer, device table, counter, graphs) alternate, so the host can fill one
+// while the other is in flight.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "me.h"
+#include "me_batch.hpp"
+#include "me_host.hpp"
+
+using namespace me;
+using namespace me::host;
+
+namespace {
+
+constexpr int kMaxJobs = 4096;
+constexpr int kSlots = 2;
+
+enum { KIND_DCDS = 1, KIND_FS = 2 };
+
+using GraphKey = std::tuple<int, int, int, int, int, size_t, int>;  // kind, B, rpl, wpg, rmax, lds, cap
+
+struct Slot {
+    BatchTable* host = nullptr;  // pinned
+    BatchTable* dev = nullptr;
+    int* counter = nullptr;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+    std::map<GraphKey, hipGraphExec_t> graphs;
+};
+
+struct BatchState {
+    std::mutex mu;
+    Slot slots[kSlots];
+    int next = 0;
+    int device = -1;
+    hipStream_t cap = nullptr;
+    int cus = 0;
+};
+BatchState g_batch;
+
+struct TuneEntry {
+    std::string arch;
+    int runtime;
+    int block, rclass, rpl, wpg;
+    float ms;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+
+int ensure_slot(Slot& s) {
+    if (s.host) return ME_OK;
+    const size_t bytes = batch_table_bytes(kMaxJobs);
+    if (hipHostMalloc(reinterpret_cast<void**>(&s.host), bytes, hipHostMallocDefault) != hipSuccess) {
+        s.host = nullptr;
+        return ME_ENOMEM;
+    }
+    if (hipMalloc(reinterpret_cast<void**>(&s.dev), bytes) != hipSuccess) {
+        s.dev = nullptr;
+        return ME_ENOMEM;
+    }
+    if (hipMalloc(reinterpret_cast<void**>(&s.counter), 64) != hipSuccess) {
+        s.counter = nullptr;
+        return ME_ENOMEM;
+    }
+    if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) return ME_EDEVICE;
+    return ME_OK;
+}
+
+int ensure_state() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return ME_EDEVICE;
+    if (g_batch.device >= 0 && g_batch.device != dev) return ME_EUNSUPPORTED;  // one device per process
+    if (g_batch.device < 0) {
+        if (hipStreamCreateWithFlags(&g_batch.cap, hipStreamNonBlocking) != hipSuccess) return ME_EDEVICE;
+        if (hipDeviceGetAttribute(&g_batch.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return ME_EDEVICE;
+        g_batch.device = dev;
+    }
+    return ME_OK;
+}
+
+// The persistent kernel of one variant, its block size, LDS bytes and grid.
+struct Variant {
+    const void* fn;
+    int threads;
+    size_t lds;
+};
+
+template <int B, int RPL, int WPG, int RMAX>
+Variant dcds_variant(int R) {
+    return Variant{reinterpret_cast<const void*>(&k_dcds_batch<B, RPL, WPG, RMAX>), 64 * WPG,
+                   dcds_lds_bytes<B, RPL, WPG, RMAX>(R) + 16};
+}
+
+template <int B, int RPL, int RMAX>
+Variant dcds_variant_w(int wpg, int R) {
+    if (wpg == 1) return dcds_variant<B, RPL, 1, RMAX>(R);
+    if (wpg == 2) return dcds_variant<B, RPL, 2, RMAX>(R);
+    return dcds_variant<B, RPL, 4, RMAX>(R);
+}
+
+template <int B, int RMAX>
+Variant dcds_variant_r(int rpl, int wpg, int R) {
+    if (rpl == 1) return dcds_variant_w<B, 1, RMAX>(wpg, R);
+    if constexpr (B == 16) {
+        if (rpl == 4) return dcds_variant_w<B, 4, RMAX>(wpg, R);
+    }
+    return dcds_variant_w<B, 2, RMAX>(wpg, R);
+}
+
+Variant pick_variant(int kind, int B, int rpl, int wpg, int R) {
+    if (kind == KIND_FS) {
+        const size_t lds = (B == 16 ? fs_lds_bytes<16>(R) : fs_lds_bytes<8>(R)) + 16;
+        return Variant{B == 16 ? reinterpret_cast<const void*>(&k_fs_batch<16>)
+                               : reinterpret_cast<const void*>(&k_fs_batch<8>),
+                       256, lds};
+    }
+    const int rc = range_class(R);
+    if (B == 16) {
+        if (rc == 0) return dcds_variant_r<16, 7>(rpl, wpg, R);
+        if (rc == 1) return dcds_variant_r<16, 15>(rpl, wpg, R);
+        return dcds_variant_r<16, 31>(rpl, wpg, R);
+    }
+    if (rc == 0) return dcds_variant_r<8, 7>(rpl, wpg, R);
+    if (rc == 1) return dcds_variant_r<8, 15>(rpl, wpg, R);
+    return dcds_variant_r<8, 31>(rpl, wpg, R);
+}
+
+// Enqueues copy + reset + persistent kernel on `st` (capturing or not).
+int enqueue(Slot& s, const Variant& v, unsigned grid, size_t table_bytes, hipStream_t st) {
+    if (hipMemcpyAsync(s.dev, s.host, table_bytes, hipMemcpyHostToDevice, st) != hipSuccess) return ME_EDEVICE;
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, s.counter);
+    void* args[] = {&s.dev, &s.counter};
+    if (hipLaunchKernel(v.fn, dim3(grid), dim3(v.threads), args, v.lds, st) != hipSuccess) return ME_EDEVICE;
+    return ME_OK;
+}
+
+int batch_launch(const me_job* jobs, int32_t n_jobs, int32_t algo, int32_t block, int32_t range, hipStream_t st) {
+    if (n_jobs < 0 || n_jobs > kMaxJobs) return ME_EINVAL;
+    if (algo != ME_ALGO_FS && algo != ME_ALGO_DCDS && algo != ME_ALGO_DCDS_S) return ME_EUNSUPPORTED;
+    if (block != 8 && block != 16) return ME_EUNSUPPORTED;
+    if (range < 1 || range > 31) return ME_EUNSUPPORTED;
+    if (n_jobs > 0 && !jobs) return ME_EINVAL;
+    for (int i = 0; i < n_jobs; ++i) {
+        const me_job& j = jobs[i];
+        const int rc = check_frames(j.cur, j.ref, j.width, j.height, j.pitch, j.pair_stride, j.n_pairs, block, range,
+                                    j.mv, j.sad, j.nsp);
+        if (rc != ME_OK) return rc;
+        if (j.orient && !j.start) return ME_EINVAL;
+        if (algo == ME_ALGO_FS && (j.start || j.orient)) return ME_EINVAL;
+    }
+    const int kind = algo == ME_ALGO_FS ? KIND_FS : KIND_DCDS;
+    int rpl = 1, wpg = 1;
+    if (kind == KIND_DCDS) current_cfg(block, range_class(range), &rpl, &wpg);
+    const int tile_w = kind == KIND_FS ? 1 : 64 * rpl / block, tile_h = kind == KIND_FS ? 1 : wpg;
+
+    // Table contents (host side, before touching shared state).
+    std::vector<BatchJob> tab;
+    tab.reserve(n_jobs);
+    long long total = 0;
+    for (int i = 0; i < n_jobs; ++i) {
+        const me_job& j = jobs[i];
+        if (j.n_pairs == 0) continue;
+        BatchJob b;
+        b.a = frame_args(j.cur, j.ref, j.width, j.height, j.pitch, j.pair_stride, block, range, tile_w, tile_h);
+        b.flags = dcds_flags(algo, j.cur, j.ref, j.width, j.pitch, j.pair_stride);
+        b.tile_begin = (int)total;
+        b.start = reinterpret_cast<const int16_t*>(j.start);
+        b.orient = j.orient;
+        b.mv = reinterpret_cast<int16_t*>(j.mv);
+        b.sad = j.sad;
+        b.nsp = j.nsp;
+        total += (long long)b.a.tiles_x * b.a.tiles_y * j.n_pairs;
+        if (total > INT32_MAX) return ME_EUNSUPPORTED;
+        tab.push_back(b);
+    }
+    if (tab.empty()) return ME_OK;
+
+    const Variant v = pick_variant(kind, block, rpl, wpg, range);
+    if (v.lds > kMaxLds) return ME_EUNSUPPORTED;
+
+    std::lock_guard<std::mutex> lock(g_batch.mu);
+    int rc = ensure_state();
+    if (rc != ME_OK) return rc;
+    Slot& s = g_batch.slots[g_batch.next];
+    g_batch.next = (g_batch.next + 1) % kSlots;
+    rc = ensure_slot(s);
+    if (rc != ME_OK) return rc;
+    if (s.pending && hipEventSynchronize(s.done) != hipSuccess) return ME_EDEVICE;
+    s.pending = false;
+
+    s.host->n_jobs = (int)tab.size();
+    s.host->total_tiles = (int)total;
+    memcpy(s.host->jobs, tab.data(), tab.size() * sizeof(BatchJob));
+    int cap = 64;
+    while (cap < (int)tab.size()) cap *= 2;
+    const size_t table_bytes = batch_table_bytes(cap);
+
+    if (v.lds > 65536 &&
+        hipFuncSetAttribute(v.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds) != hipSuccess)
+        return ME_EUNSUPPORTED;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, v.fn, v.threads, v.lds) != hipSuccess || per_cu < 1)
+        return ME_EUNSUPPORTED;
+    const unsigned grid = (unsigned)(per_cu * g_batch.cus);
+
+    const GraphKey key{kind, block, rpl, wpg, range_class(range), v.lds, cap};
+    auto it = s.graphs.find(key);
+    if (it == s.graphs.end()) {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        bool ok = hipStreamBeginCapture(g_batch.cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            const int erc = enqueue(s, v, grid, table_bytes, g_batch.cap);
+            ok = hipStreamEndCapture(g_batch.cap, &graph) == hipSuccess && erc == ME_OK && graph;
+        }
+        if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        it = s.graphs.emplace(key, ok ? exec : nullptr).first;
+    }
+    if (it->second) {
+        if (hipGraphLaunch(it->second, st) != hipSuccess) return ME_EDEVICE;
+    } else {
+        // Capture unavailable: the same three steps as direct launches.
+        rc = enqueue(s, v, grid, table_bytes, st);
+        if (rc != ME_OK) return rc;
+    }
+    if (hipEventRecord(s.done, st) != hipSuccess) return ME_EDEVICE;
+    s.pending = true;
+    return ME_OK;
+}
+
+int device_identity(std::string* arch, int* runtime) {
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return ME_EDEVICE;
+    if (hipRuntimeGetVersion(runtime) != hipSuccess) return ME_EDEVICE;
+    *arch = p.gcnArchName;
+    const size_t colon = arch->find(':');
+    if (colon != std::string::npos) arch->resize(colon);
+    return ME_OK;
+}
+
+}  // namespace
+
+ME_EXPORT int me_batch(const me_job* jobs, int32_t n_jobs, int32_t algo, int32_t block, int32_t range, void* stream) {
+    return batch_launch(jobs, n_jobs, algo, block, range, reinterpret_cast<hipStream_t>(stream));
+}
+
+ME_EXPORT int me_autotune(const me_job* jobs, int32_t n_jobs, int32_t algo, int32_t block, int32_t range,
+                          int32_t reps, me_config* best, float* best_ms, void* stream) {
+    if (algo != ME_ALGO_DCDS && algo != ME_ALGO_DCDS_S) return ME_EUNSUPPORTED;
+    if (block != 8 && block != 16) return ME_EUNSUPPORTED;
+    if (range < 1 || range > 31) return ME_EUNSUPPORTED;
+    if (reps < 1 || n_jobs < 1 || !jobs) return ME_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return ME_EDEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return ME_EDEVICE;
+    }
+    me_config saved;
+    me_get_config(block, range, &saved);
+    me_config top{0, 0};
+    float top_ms = 0.f;
+    int rc = ME_OK;
+    const int rpls[3] = {1, 2, 4};
+    const int wpgs[3] = {1, 2, 4};
+    for (int ri = 0; ri < 3 && rc == ME_OK; ++ri) {
+        for (int wi = 0; wi < 3 && rc == ME_OK; ++wi) {
+            me_config c{rpls[ri], wpgs[wi]};
+            if (me_set_config(block, range, &c) != ME_OK) continue;
+            int r = batch_launch(jobs, n_jobs, algo, block, range, st);  // warm-up, builds the graph
+            if (r == ME_EUNSUPPORTED) continue;
+            if (r != ME_OK) {
+                rc = r;
+                break;
+            }
+            if (hipEventRecord(e0, st) != hipSuccess) rc = ME_EDEVICE;
+            for (int i = 0; i < reps && rc == ME_OK; ++i) rc = batch_launch(jobs, n_jobs, algo, block, range, st);
+            if (rc == ME_OK && hipEventRecord(e1, st) != hipSuccess) rc = ME_EDEVICE;
+            if (rc == ME_OK && hipEventSynchronize(e1) != hipSuccess) rc = ME_EDEVICE;
+            float ms = 0.f;
+            if (rc == ME_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = ME_EDEVICE;
+            ms /= (float)reps;
+            if (rc == ME_OK && (top.rows_per_lane == 0 || ms < top_ms)) {
+                top = c;
+                top_ms = ms;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != ME_OK || top.rows_per_lane == 0) {
+        me_set_config(block, range, &saved);
+        return rc != ME_OK ? rc : ME_EUNSUPPORTED;
+    }
+    me_set_config(block, range, &top);
+    if (best) *best = top;
+    if (best_ms) *best_ms = top_ms;
+    TuneEntry e;
+    if (device_identity(&e.arch, &e.runtime) == ME_OK) {
+        e.block = block;
+        e.rclass = range_class(range);
+        e.rpl = top.rows_per_lane;
+        e.wpg = top.waves_per_group;
+        e.ms = top_ms;
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        bool replaced = false;
+        for (auto& t : g_tune) {
+            if (t.arch == e.arch && t.runtime == e.runtime && t.block == e.block && t.rclass == e.rclass) {
+                t = e;
+                replaced = true;
+            }
+        }
+        if (!replaced) g_tune.push_back(e);
+    }
+    return ME_OK;
+}
+
+ME_EXPORT int me_autotune_save(const char* path) {
+    if (!path) return ME_EINVAL;
+    FILE* f = fopen(path, "w");
+    if (!f) return ME_EINVAL;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    fprintf(f, "# me autotune cache v1: arch runtime block range_class rows_per_lane waves_per_group ms\n");
+    for (const auto& t : g_tune)
+        fprintf(f, "%s %d %d %d %d %d %.6f\n", t.arch.c_str(), t.runtime, t.block, t.rclass, t.rpl, t.wpg, t.ms);
+    const int bad = ferror(f);
+    fclose(f);
+    return bad ? ME_EINVAL : ME_OK;
+}
+
+ME_EXPORT int me_autotune_load(const char* path, int32_t* applied, int32_t* rejected) {
+    if (!path) return ME_EINVAL;
+    if (applied) *applied = 0;
+    if (rejected) *rejected = 0;
+    FILE* f = fopen(path, "r");
+    if (!f) return ME_EINVAL;
+    std::string arch;
+    int runtime = 0;
+    const bool have_id = device_identity(&arch, &runtime) == ME_OK;
+    char line[512];
+    int n_ok = 0, n_bad = 0;
+    while (fgets(line, sizeof line, f)) {
+        if (line[0] == '#' || line[0] == '\n') continue;
+        char a[128];
+        int rt, blk, rcl, rpl, wpg;
+        float ms;
+        if (sscanf(line, "%127s %d %d %d %d %d %f", a, &rt, &blk, &rcl, &rpl, &wpg, &ms) != 7 || rcl < 0 || rcl > 2 ||
+            (blk != 8 && blk != 16) || !valid_cfg(blk, rpl, wpg)) {
+            ++n_bad;
+            continue;
+        }
+        if (!have_id || arch != a || rt != runtime) continue;  // tuned on other hardware or runtime
+        const int rep_range = rcl == 0 ? 7 : (rcl == 1 ? 15 : 31);
+        me_config c{rpl, wpg};
+        if (me_set_config(blk, rep_range, &c) == ME_OK) {
+            ++n_ok;
+            std::lock_guard<std::mutex> lock(g_tune_mu);
+            g_tune.push_back(TuneEntry{a, rt, blk, rcl, rpl, wpg, ms});
+        }
+    }
+    fclose(f);
+    if (applied) *applied = n_ok;
+    if (rejected) *rejected = n_bad;
+    return ME_OK;
+}
+
+ME_EXPORT int me_shutdown(void) {
+    std::lock_guard<std::mutex> lock(g_batch.mu);
+    int rc = ME_OK;
+    for (auto& s : g_batch.slots) {
+        if (s.pending && hipEventSynchronize(s.done) != hipSuccess) rc = ME_EDEVICE;
+        s.pending = false;
+        for (auto& kv : s.graphs)
+            if (kv.second) (void)hipGraphExecDestroy(kv.second);
+        s.graphs.clear();
+        if (s.host) (void)hipHostFree(s.host);
+        if (s.dev) (void)hipFree(s.dev);
+        if (s.counter) (void)hipFree(s.counter);
+        if (s.done) (void)hipEventDestroy(s.done);
+        s.host = nullptr;
+        s.dev = nullptr;
+        s.counter = nullptr;
+        s.done = nullptr;
+    }
+    if (g_batch.cap) (void)hipStreamDestroy(g_batch.cap);
+    g_batch.cap = nullptr;
+    g_batch.device = -1;
+    return rc;
+}

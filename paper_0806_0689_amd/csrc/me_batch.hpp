@@ -1,0 +1,94 @@
+// Persistent kernels over a device job table: many frame sequences of any
+// size in one launch.  Each workgroup takes the next tile from an atomic
+// counter until the table is exhausted, so streams of uneven resolution share
+// the GPU without per-stream launches.
+#pragma once
+
+#include "me_kernels.hpp"
+
+namespace me {
+
+struct BatchJob {
+    FrameArgs a;             // geometry of this job (tiles per the current configuration)
+    int flags;               // DCDS flags (simplified, 16-byte loads)
+    int tile_begin;          // first tile of this job in the flattened index space
+    const int16_t* start;    // optional learned start vectors
+    const uint8_t* orient;   // optional first-cross orientations
+    int16_t* mv;
+    uint32_t* sad;
+    uint32_t* nsp;
+};
+
+struct BatchTable {
+    int n_jobs;
+    int total_tiles;
+    int pad0, pad1;
+    BatchJob jobs[1];  // n_jobs entries (the allocation holds the capacity)
+};
+
+__host__ __device__ constexpr size_t batch_table_bytes(int cap) {
+    return sizeof(BatchTable) + (size_t)(cap - 1) * sizeof(BatchJob);
+}
+
+static __global__ void k_batch_reset(int* counter) {
+    if (threadIdx.x == 0) counter[0] = 0;
+}
+
+// Index of the job holding tile t: the last job whose tile_begin <= t.
+__device__ __forceinline__ int batch_job_of(const BatchTable* tab, int t) {
+    int lo = 0, hi = tab->n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab->jobs[mid].tile_begin <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Takes the next tile for the whole workgroup; every wave leaves the previous
+// tile (and its LDS) before the new index is published.
+__device__ __forceinline__ int batch_next(int* counter, int* s_tile) {
+    __syncthreads();
+    if (threadIdx.x == 0) *s_tile = atomicAdd(counter, 1);
+    __syncthreads();
+    return *s_tile;
+}
+
+template <int B, int RPL, int WPG, int RMAX>
+__global__ __launch_bounds__(64 * WPG) void k_dcds_batch(const BatchTable* __restrict__ tab, int* __restrict__ counter) {
+    extern __shared__ uint32_t smem[];
+    __shared__ int s_tile;
+    const int total = tab->total_tiles;
+    for (;;) {
+        const int t = batch_next(counter, &s_tile);
+        if (t >= total) break;
+        const BatchJob& jb = tab->jobs[batch_job_of(tab, t)];
+        int r = t - jb.tile_begin;
+        const int tx = r % jb.a.tiles_x;
+        r /= jb.a.tiles_x;
+        const int ty = r % jb.a.tiles_y;
+        const int pair = r / jb.a.tiles_y;
+        dcds_tile<B, RPL, WPG, RMAX>(smem, jb.a, jb.flags, pair, tx, ty, jb.start, jb.orient, jb.mv, jb.sad,
+                                     jb.nsp);
+    }
+}
+
+template <int B>
+__global__ __launch_bounds__(256) void k_fs_batch(const BatchTable* __restrict__ tab, int* __restrict__ counter) {
+    extern __shared__ uint32_t smem[];
+    __shared__ int s_tile;
+    const int total = tab->total_tiles;
+    for (;;) {
+        const int t = batch_next(counter, &s_tile);
+        if (t >= total) break;
+        const BatchJob& jb = tab->jobs[batch_job_of(tab, t)];
+        int r = t - jb.tile_begin;
+        const int bx = r % jb.a.bw;
+        r /= jb.a.bw;
+        const int by = r % jb.a.bh;
+        const int pair = r / jb.a.bh;
+        fs_block<B>(smem, jb.a, pair, bx, by, jb.mv, jb.sad, jb.nsp);
+    }
+}
+
+}  // namespace me

@@ -209,23 +209,20 @@ __device__ __forceinline__ int xcd_remap(int i, int n) {
 // flags: DCDS_SIMPLIFIED (Step 4 of DCDS^S), DCDS_VEC16 (16-byte loads allowed).
 enum { DCDS_SIMPLIFIED = 1, DCDS_VEC16 = 2 };
 
+// One tile (BPW x WPG blocks) of one frame pair.  All threads of the
+// workgroup call it; it ends with every wave done with the LDS window except
+// for the final search, so callers that loop must barrier before restaging.
 template <int B, int RPL, int WPG, int RMAX>
-__global__ __launch_bounds__(64 * WPG) void k_dcds(FrameArgs a, int flags, const int16_t* __restrict__ start,
-                                                    const uint8_t* __restrict__ orient, int16_t* __restrict__ mv,
-                                                    uint32_t* __restrict__ sad, uint32_t* __restrict__ nsp) {
+__device__ __forceinline__ void dcds_tile(uint32_t* smem, const FrameArgs& a, int flags, int pair, int tx, int ty,
+                                          const int16_t* __restrict__ start, const uint8_t* __restrict__ orient,
+                                          int16_t* __restrict__ mv, uint32_t* __restrict__ sad,
+                                          uint32_t* __restrict__ nsp) {
     using G = DcdsGeo<B, RPL, WPG, RMAX>;
     constexpr int L = G::L, K = G::K;
-    extern __shared__ uint32_t smem[];
     const int R = a.R;
     const int BMW = bitmap_words(R);
     uint32_t* win = smem;
     uint32_t* bms = smem + G::WIN_WORDS;
-
-    int t = xcd_remap(blockIdx.x, gridDim.x);
-    const int tx = t % a.tiles_x;
-    t /= a.tiles_x;
-    const int ty = t % a.tiles_y;
-    const int pair = t / a.tiles_y;
     const uint8_t* curf = a.cur + (long long)pair * a.pair_stride;
     const uint8_t* reff = a.ref + (long long)pair * a.pair_stride;
     const int X0 = tx * G::TW, Y0 = ty * G::TH;
@@ -266,30 +263,43 @@ __global__ __launch_bounds__(64 * WPG) void k_dcds(FrameArgs a, int flags, const
     Roles<L> ro;
     ro.init(g);
     __syncthreads();
-    if (!exists) return;
+    if (exists) {
+        Bounds bd;
+        bd.lox = max(-R, -x0);
+        bd.hix = min(R, a.W - B - x0);
+        bd.loy = max(-R, -y0);
+        bd.hiy = min(R, a.H - B - y0);
+        const long long idx = ((long long)pair * a.bh + by) * a.bw + bx;
+        const bool seeded = start != nullptr;
+        int sx = 0, sy = 0;
+        bool ov = false;
+        if (seeded) {
+            sx = start[2 * idx];
+            sy = start[2 * idx + 1];
+            ov = orient != nullptr && orient[idx] != 0;
+        }
+        const SearchOut r =
+            dcds_search<L>(ev, R, bd, bm, ro, b * L, (flags & DCDS_SIMPLIFIED) != 0, seeded, sx, sy, ov);
+        if (g == 0) {
+            mv[2 * idx] = (int16_t)r.x;
+            mv[2 * idx + 1] = (int16_t)r.y;
+            sad[idx] = r.cost;
+            nsp[idx] = r.nsp;
+        }
+    }
+}
 
-    Bounds bd;
-    bd.lox = max(-R, -x0);
-    bd.hix = min(R, a.W - B - x0);
-    bd.loy = max(-R, -y0);
-    bd.hiy = min(R, a.H - B - y0);
-    const long long idx = ((long long)pair * a.bh + by) * a.bw + bx;
-    const bool seeded = start != nullptr;
-    int sx = 0, sy = 0;
-    bool ov = false;
-    if (seeded) {
-        sx = start[2 * idx];
-        sy = start[2 * idx + 1];
-        ov = orient != nullptr && orient[idx] != 0;
-    }
-    const SearchOut r =
-        dcds_search<L>(ev, R, bd, bm, ro, b * L, (flags & DCDS_SIMPLIFIED) != 0, seeded, sx, sy, ov);
-    if (g == 0) {
-        mv[2 * idx] = (int16_t)r.x;
-        mv[2 * idx + 1] = (int16_t)r.y;
-        sad[idx] = r.cost;
-        nsp[idx] = r.nsp;
-    }
+template <int B, int RPL, int WPG, int RMAX>
+__global__ __launch_bounds__(64 * WPG) void k_dcds(FrameArgs a, int flags, const int16_t* __restrict__ start,
+                                                    const uint8_t* __restrict__ orient, int16_t* __restrict__ mv,
+                                                    uint32_t* __restrict__ sad, uint32_t* __restrict__ nsp) {
+    extern __shared__ uint32_t smem[];
+    int t = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = t % a.tiles_x;
+    t /= a.tiles_x;
+    const int ty = t % a.tiles_y;
+    const int pair = t / a.tiles_y;
+    dcds_tile<B, RPL, WPG, RMAX>(smem, a, flags, pair, tx, ty, start, orient, mv, sad, nsp);
 }
 
 }  // namespace me

@@ -22,103 +22,6 @@ __device__ __forceinline__ void stage_window(uint32_t* dst, const uint8_t* frame
 }
 
 // ---------------------------------------------------------------------------
-// DCDS over cost surfaces (ideal-condition analysis of §III-C).  16 lanes per
-// surface; the "distortion" of a point is read from the caller's table.
-// Points outside the window are clamped to it for the read (they are masked).
-// ---------------------------------------------------------------------------
-struct SurfaceEval {
-    const int32_t* cost;
-    int R;
-    __device__ __forceinline__ uint32_t at(int x, int y) const {
-        x = clampi(x, -R, R);
-        y = clampi(y, -R, R);
-        return (uint32_t)cost[(y + R) * (2 * R + 1) + (x + R)];
-    }
-    __device__ __forceinline__ void cross(int cx, int cy, bool t, uint32_t (&c)[7]) const {
-        const int ax = t ? 0 : 1, ay = t ? 1 : 0;
-        c[0] = at(cx, cy);
-        c[1] = at(cx - ax, cy - ay);
-        c[2] = at(cx + ax, cy + ay);
-        c[3] = at(cx - 2 * ax, cy - 2 * ay);
-        c[4] = at(cx + 2 * ax, cy + 2 * ay);
-        c[5] = at(cx - ay, cy - ax);
-        c[6] = at(cx + ay, cy + ax);
-    }
-    __device__ __forceinline__ void cross0(uint32_t (&c)[7]) const { cross(0, 0, false, c); }
-    __device__ __forceinline__ void diamond(int cx, int cy, bool t, uint32_t (&c)[4]) const {
-        const int ax = t ? 0 : 1, ay = t ? 1 : 0;
-        c[0] = at(cx - 2 * ax, cy - 2 * ay);
-        c[1] = at(cx + 2 * ax, cy + 2 * ay);
-        c[2] = at(cx - ay, cy - ax);
-        c[3] = at(cx + ay, cy + ax);
-    }
-    __device__ __forceinline__ void mids(int cx, int cy, bool t, uint32_t (&c)[2]) const {
-        const int ax = t ? 0 : 1, ay = t ? 1 : 0;
-        c[0] = at(cx - ax, cy - ay);
-        c[1] = at(cx + ax, cy + ay);
-    }
-    __device__ __forceinline__ void probe(int sx, int sy, uint32_t (&c)[2]) const {
-        c[0] = at(0, 0);
-        c[1] = at(sx, sy);
-    }
-};
-
-__global__ __launch_bounds__(256) void k_dcds_surface(const int32_t* __restrict__ cost, const uint8_t* __restrict__ valid,
-                                                      int n, int R, bool simplified, const int16_t* __restrict__ start,
-                                                      const uint8_t* __restrict__ orient, int16_t* __restrict__ mv,
-                                                      uint32_t* __restrict__ out_cost, uint32_t* __restrict__ nsp) {
-    constexpr int L = 16;
-    extern __shared__ uint32_t smem[];
-    const int BMW = bitmap_words(R);
-    const int gi = threadIdx.x / L, g = threadIdx.x % L;
-    const long long s = (long long)blockIdx.x * (256 / L) + gi;
-    uint32_t* bm = smem + gi * BMW;
-    for (int i = g; i < BMW; i += L) bm[i] = 0u;
-    Roles<L> ro;
-    ro.init(g);
-    __syncthreads();
-    if (s >= n) return;
-    const int side = 2 * R + 1;
-    SurfaceEval ev{cost + s * side * side, R};
-    // The candidate set is the bounding box of the valid mask, plus the origin.
-    Bounds bd{-R, R, -R, R};
-    if (valid) {
-        const uint8_t* vm = valid + s * side * side;
-        int lox = R + 1, hix = -R - 1, loy = R + 1, hiy = -R - 1;
-        for (int i = g; i < side * side; i += L) {
-            if (vm[i]) {
-                const int yy = i / side - R, xx = i % side - R;
-                lox = min(lox, xx);
-                hix = max(hix, xx);
-                loy = min(loy, yy);
-                hiy = max(hiy, yy);
-            }
-        }
-        // The origin always belongs to the set (keeps every read in the table).
-        bd.lox = min(0, (int)group_min<16>((uint32_t)(lox + 64)) - 64);
-        bd.hix = max(0, 64 - (int)group_min<16>((uint32_t)(64 - hix)));
-        bd.loy = min(0, (int)group_min<16>((uint32_t)(loy + 64)) - 64);
-        bd.hiy = max(0, 64 - (int)group_min<16>((uint32_t)(64 - hiy)));
-    }
-    const bool seeded = start != nullptr;
-    int sx = 0, sy = 0;
-    bool ov = false;
-    if (seeded) {
-        sx = start[2 * s];
-        sy = start[2 * s + 1];
-        ov = orient != nullptr && orient[s] != 0;
-    }
-    const int lane = threadIdx.x & 63;
-    const SearchOut r = dcds_search<L>(ev, R, bd, bm, ro, (lane / L) * L, simplified, seeded, sx, sy, ov);
-    if (g == 0) {
-        mv[2 * s] = (int16_t)r.x;
-        mv[2 * s + 1] = (int16_t)r.y;
-        out_cost[s] = r.cost;
-        nsp[s] = r.nsp;
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Full search.  One workgroup per block.  Work item (y, g): candidate row y
 // and four horizontally adjacent candidates x = x_g .. x_g + 3, all four
 // evaluated at once by v_qsad_pk_u16_u8 on an 8-byte reference window
@@ -137,10 +40,11 @@ __device__ __forceinline__ uint32_t fs_key(uint32_t s, int x, int y) {
     return (s << 13) | ((uint32_t)(abs(x) + abs(y)) << 7) | ((uint32_t)(y + 31) << 1) | (x > 0 ? 1u : 0u);
 }
 
+// One block of one frame pair; all 256 threads of the workgroup call it.
 template <int B>
-__global__ __launch_bounds__(256) void k_fs(FrameArgs a, int16_t* __restrict__ mv, uint32_t* __restrict__ sad,
-                                            uint32_t* __restrict__ nsp) {
-    extern __shared__ uint32_t smem[];
+__device__ __forceinline__ void fs_block(uint32_t* smem, const FrameArgs& a, int pair, int bx, int by,
+                                         int16_t* __restrict__ mv, uint32_t* __restrict__ sad,
+                                         uint32_t* __restrict__ nsp) {
     const int R = a.R;
     const int MW = margin_words(R);
     const int G = fs_groups(R);
@@ -150,11 +54,6 @@ __global__ __launch_bounds__(256) void k_fs(FrameArgs a, int16_t* __restrict__ m
     uint32_t* curs = smem + WR * WD;
     uint32_t* part = curs + B * B / 4;
 
-    int t = blockIdx.x;
-    const int bx = t % a.bw;
-    t /= a.bw;
-    const int by = t % a.bh;
-    const int pair = t / a.bh;
     const uint8_t* curf = a.cur + (long long)pair * a.pair_stride;
     const uint8_t* reff = a.ref + (long long)pair * a.pair_stride;
     const int x0 = bx * B, y0 = by * B;
@@ -204,6 +103,18 @@ __global__ __launch_bounds__(256) void k_fs(FrameArgs a, int16_t* __restrict__ m
         sad[idx] = k >> 13;
         nsp[idx] = (uint32_t)((hix - lox + 1) * (hiy - loy + 1));
     }
+}
+
+template <int B>
+__global__ __launch_bounds__(256) void k_fs(FrameArgs a, int16_t* __restrict__ mv, uint32_t* __restrict__ sad,
+                                            uint32_t* __restrict__ nsp) {
+    extern __shared__ uint32_t smem[];
+    int t = blockIdx.x;
+    const int bx = t % a.bw;
+    t /= a.bw;
+    const int by = t % a.bh;
+    const int pair = t / a.bh;
+    fs_block<B>(smem, a, pair, bx, by, mv, sad, nsp);
 }
 
 }  // namespace me

@@ -1,0 +1,106 @@
+// DCDS over caller cost surfaces (the ideal-condition analysis of §III-C on
+// the device).
+#pragma once
+
+#include "me_dcds.hpp"
+
+namespace me {
+
+// ---------------------------------------------------------------------------
+// DCDS over cost surfaces (ideal-condition analysis of §III-C).  16 lanes per
+// surface; the "distortion" of a point is read from the caller's table.
+// Points outside the window are clamped to it for the read (they are masked).
+// ---------------------------------------------------------------------------
+struct SurfaceEval {
+    const int32_t* cost;
+    int R;
+    __device__ __forceinline__ uint32_t at(int x, int y) const {
+        x = clampi(x, -R, R);
+        y = clampi(y, -R, R);
+        return (uint32_t)cost[(y + R) * (2 * R + 1) + (x + R)];
+    }
+    __device__ __forceinline__ void cross(int cx, int cy, bool t, uint32_t (&c)[7]) const {
+        const int ax = t ? 0 : 1, ay = t ? 1 : 0;
+        c[0] = at(cx, cy);
+        c[1] = at(cx - ax, cy - ay);
+        c[2] = at(cx + ax, cy + ay);
+        c[3] = at(cx - 2 * ax, cy - 2 * ay);
+        c[4] = at(cx + 2 * ax, cy + 2 * ay);
+        c[5] = at(cx - ay, cy - ax);
+        c[6] = at(cx + ay, cy + ax);
+    }
+    __device__ __forceinline__ void cross0(uint32_t (&c)[7]) const { cross(0, 0, false, c); }
+    __device__ __forceinline__ void diamond(int cx, int cy, bool t, uint32_t (&c)[4]) const {
+        const int ax = t ? 0 : 1, ay = t ? 1 : 0;
+        c[0] = at(cx - 2 * ax, cy - 2 * ay);
+        c[1] = at(cx + 2 * ax, cy + 2 * ay);
+        c[2] = at(cx - ay, cy - ax);
+        c[3] = at(cx + ay, cy + ax);
+    }
+    __device__ __forceinline__ void mids(int cx, int cy, bool t, uint32_t (&c)[2]) const {
+        const int ax = t ? 0 : 1, ay = t ? 1 : 0;
+        c[0] = at(cx - ax, cy - ay);
+        c[1] = at(cx + ax, cy + ay);
+    }
+    __device__ __forceinline__ void probe(int sx, int sy, uint32_t (&c)[2]) const {
+        c[0] = at(0, 0);
+        c[1] = at(sx, sy);
+    }
+};
+
+__global__ __launch_bounds__(256) void k_dcds_surface(const int32_t* __restrict__ cost, const uint8_t* __restrict__ valid,
+                                                      int n, int R, bool simplified, const int16_t* __restrict__ start,
+                                                      const uint8_t* __restrict__ orient, int16_t* __restrict__ mv,
+                                                      uint32_t* __restrict__ out_cost, uint32_t* __restrict__ nsp) {
+    constexpr int L = 16;
+    extern __shared__ uint32_t smem[];
+    const int BMW = bitmap_words(R);
+    const int gi = threadIdx.x / L, g = threadIdx.x % L;
+    const long long s = (long long)blockIdx.x * (256 / L) + gi;
+    uint32_t* bm = smem + gi * BMW;
+    for (int i = g; i < BMW; i += L) bm[i] = 0u;
+    Roles<L> ro;
+    ro.init(g);
+    __syncthreads();
+    if (s >= n) return;
+    const int side = 2 * R + 1;
+    SurfaceEval ev{cost + s * side * side, R};
+    // The candidate set is the bounding box of the valid mask, plus the origin.
+    Bounds bd{-R, R, -R, R};
+    if (valid) {
+        const uint8_t* vm = valid + s * side * side;
+        int lox = R + 1, hix = -R - 1, loy = R + 1, hiy = -R - 1;
+        for (int i = g; i < side * side; i += L) {
+            if (vm[i]) {
+                const int yy = i / side - R, xx = i % side - R;
+                lox = min(lox, xx);
+                hix = max(hix, xx);
+                loy = min(loy, yy);
+                hiy = max(hiy, yy);
+            }
+        }
+        // The origin always belongs to the set (keeps every read in the table).
+        bd.lox = min(0, (int)group_min<16>((uint32_t)(lox + 64)) - 64);
+        bd.hix = max(0, 64 - (int)group_min<16>((uint32_t)(64 - hix)));
+        bd.loy = min(0, (int)group_min<16>((uint32_t)(loy + 64)) - 64);
+        bd.hiy = max(0, 64 - (int)group_min<16>((uint32_t)(64 - hiy)));
+    }
+    const bool seeded = start != nullptr;
+    int sx = 0, sy = 0;
+    bool ov = false;
+    if (seeded) {
+        sx = start[2 * s];
+        sy = start[2 * s + 1];
+        ov = orient != nullptr && orient[s] != 0;
+    }
+    const int lane = threadIdx.x & 63;
+    const SearchOut r = dcds_search<L>(ev, R, bd, bm, ro, (lane / L) * L, simplified, seeded, sx, sy, ov);
+    if (g == 0) {
+        mv[2 * s] = (int16_t)r.x;
+        mv[2 * s + 1] = (int16_t)r.y;
+        out_cost[s] = r.cost;
+        nsp[s] = r.nsp;
+    }
+}
+
+}  // namespace me

@@ -124,3 +124,43 @@ def test_config_set_get_and_checks():
     assert me.me_set_config(12, 15, (2, 2)) == me.ME_EUNSUPPORTED
     assert me.me_set_config(16, 0, (2, 2)) == me.ME_EUNSUPPORTED
     assert me.lib().me_get_config(16, 15, None) == me.ME_EINVAL
+
+
+def test_batch_argument_checks():
+    J = me.MeJob
+    good = J(P, P, 64, 32, 64, 1, 64 * 32, P, P, P, None, None)
+    arr = (J * 2)(good, good)
+    assert me.me_batch(None, -1, me.ME_ALGO_DCDS, 16, 7) == me.ME_EINVAL
+    assert me.me_batch(None, me.MAX_JOBS + 1, me.ME_ALGO_DCDS, 16, 7) == me.ME_EINVAL
+    assert me.me_batch(None, 1, me.ME_ALGO_DCDS, 16, 7) == me.ME_EINVAL
+    assert me.me_batch(None, 0, me.ME_ALGO_DCDS, 16, 7) == me.ME_OK     # empty batch
+    assert me.me_batch(arr, 2, 9, 16, 7) == me.ME_EUNSUPPORTED
+    assert me.me_batch(arr, 2, me.ME_ALGO_DCDS, 12, 7) == me.ME_EUNSUPPORTED
+    assert me.me_batch(arr, 2, me.ME_ALGO_DCDS, 16, 40) == me.ME_EUNSUPPORTED
+    bad = (J * 2)(good, J(P, P, 60, 32, 64, 1, 64 * 32, P, P, P, None, None))   # width not a multiple of 16
+    assert me.me_batch(bad, 2, me.ME_ALGO_DCDS, 16, 7) == me.ME_EINVAL
+    bad = (J * 1)(J(P, P, 64, 32, 64, 1, 64 * 32, P, P, P, None, P))           # orient without start
+    assert me.me_batch(bad, 1, me.ME_ALGO_DCDS, 16, 7) == me.ME_EINVAL
+    bad = (J * 1)(J(P, P, 64, 32, 64, 1, 64 * 32, P, P, P, P, None))           # start with FS
+    assert me.me_batch(bad, 1, me.ME_ALGO_FS, 16, 7) == me.ME_EINVAL
+    empty = (J * 1)(J(None, None, 64, 32, 64, 0, 0, None, None, None, None, None))  # zero pairs
+    assert me.me_batch(empty, 1, me.ME_ALGO_DCDS, 16, 7) == me.ME_OK
+
+
+def test_autotune_argument_checks(tmp_path):
+    J = me.MeJob
+    arr = (J * 1)(J(P, P, 64, 32, 64, 1, 64 * 32, P, P, P, None, None))
+    assert me.me_autotune(arr, 1, me.ME_ALGO_FS, 16, 7, 3)[0] == me.ME_EUNSUPPORTED
+    assert me.me_autotune(arr, 1, me.ME_ALGO_DCDS, 12, 7, 3)[0] == me.ME_EUNSUPPORTED
+    assert me.me_autotune(arr, 1, me.ME_ALGO_DCDS, 16, 0, 3)[0] == me.ME_EUNSUPPORTED
+    assert me.me_autotune(arr, 1, me.ME_ALGO_DCDS, 16, 7, 0)[0] == me.ME_EINVAL
+    assert me.me_autotune(None, 0, me.ME_ALGO_DCDS, 16, 7, 3)[0] == me.ME_EINVAL
+    # Cache file: missing -> EINVAL (defaults stay); malformed lines are counted and skipped.
+    assert me.me_autotune_load(str(tmp_path / "missing.txt"))[0] == me.ME_EINVAL
+    f = tmp_path / "cache.txt"
+    f.write_text("# header\nnot a line\ngfx950 70000000 16 1 3 4 0.1\ngfx950 70000000 16 9 2 4 0.1\n"
+                 "otherarch 1 16 1 2 4 0.5\n")
+    rc, applied, rejected = me.me_autotune_load(str(f))
+    assert rc == me.ME_OK and rejected == 3 and applied == 0
+    assert me.me_autotune_save(str(tmp_path / "out.txt")) == me.ME_OK
+    assert (tmp_path / "out.txt").read_text().startswith("# me autotune cache v1")
