@@ -93,13 +93,48 @@ def cpu_baseline(seq, budget_s=12.0):
     return dcds
 
 
+def batch_leg(me, torch, dev, args):
+    """64 streams (16 each of 176x144, 352x288, 1280x720, 1920x1088), 30 frames,
+    16x16 blocks, +-15: all 29 pairs of every stream in one me_batch launch,
+    against one me_dcds call per stream."""
+    from synth import batch_streams
+    t0 = time.perf_counter()
+    seqs = [torch.from_numpy(s).to(dev) for s in batch_streams(64, 30)]
+    print("# generated 64 streams in %.1f s" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
+    pairs = [(s[1:], s[:-1]) for s in seqs]
+    blocks = sum((s.shape[0] - 1) * (s.shape[1] // 16) * (s.shape[2] // 16) for s in seqs)
+    jobs, outs = me.make_jobs(pairs, 16)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def launch():
+        rc = me.me_batch(jobs, len(pairs), me.ME_ALGO_DCDS, 16, RANGE, stream)
+        assert rc == 0, rc
+
+    def per_stream():
+        for (c, r), o in zip(pairs, outs):
+            me.dcds(c, r, 16, RANGE, out=o)
+
+    steps = max(3, min(args.steps, 20))
+    _, ms_batch, _ = time_launches(launch, steps, args.warmup, torch)
+    _, ms_loop, _ = time_launches(per_stream, steps, args.warmup, torch)
+    cfg = me.me_get_config(16, RANGE)
+    nsp = sum(float(o[2].double().sum()) for o in outs) / blocks
+    res = {"streams": 64, "frames": 30, "blocks_per_launch": blocks, "ms_per_launch": ms_batch,
+           "mb_per_s": blocks / (ms_batch * 1e-3), "per_stream_calls_ms": ms_loop,
+           "per_stream_calls_mb_per_s": blocks / (ms_loop * 1e-3), "nsp_mean": nsp,
+           "config": {"rows_per_lane": cfg[0], "waves_per_group": cfg[1]}}
+    print("# batch: %.4f ms per launch (%.3g MB/s); 64 separate calls %.4f ms" % (
+        ms_batch, res["mb_per_s"], ms_loop), file=sys.stderr, flush=True)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", default="", help="comma list of extra legs to run (fs,dcds8,dcds_s); dcds always runs")
+    ap.add_argument("--only", default="", help="comma list of extra legs to run (fs,dcds8,dcds_s,batch); dcds always runs")
     ap.add_argument("--sweep", action="store_true",
                     help="time every DCDS kernel configuration (rows per lane x waves per group) and exit")
     ap.add_argument("--calib-copy", action="store_true",
@@ -123,7 +158,7 @@ def main():
     seq = torch.from_numpy(seq_np).to(dev)
     cur, ref = seq[1:], seq[:-1]
     P = FRAMES - 1
-    legs = set(args.only.split(",")) if args.only else {"dcds", "fs", "dcds8", "dcds_s"}
+    legs = set(args.only.split(",")) if args.only else {"dcds", "fs", "dcds8", "dcds_s", "batch"}
     if args.calib_copy:
         src = torch.ones(256 << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -175,6 +210,8 @@ def main():
         leg("dcds8", lambda: me.dcds(cur, ref, 8, RANGE), args.steps, blocks8)
     if "dcds_s" in legs:
         leg("dcds_s", lambda: me.dcds(cur, ref, 16, RANGE, algo=me.ME_ALGO_DCDS_S), args.steps, blocks16)
+    if "batch" in legs:
+        results["batch"] = batch_leg(me, torch, dev, args)
     if "fs" in legs:
         fs_sad = results["fs"]["sad_mean"]
         for k in ("dcds", "dcds_s"):
@@ -206,7 +243,7 @@ def main():
         },
         "algos": results,
         "roofline": {
-            "kernel": "k_dcds<16,4,1>",
+            "kernel": "k_dcds<16,%d,%d,15>" % me.me_get_config(16, RANGE),
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

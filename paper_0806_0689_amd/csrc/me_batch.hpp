@@ -45,11 +45,16 @@ __device__ __forceinline__ int batch_job_of(const BatchTable* tab, int t) {
     return lo;
 }
 
-// Takes the next tile for the whole workgroup; every wave leaves the previous
+// Tiles are taken CHUNK at a time: one atomic and one job lookup serve
+// several tiles, which are then walked in order (crossing job boundaries with
+// one comparison each).
+constexpr int kBatchChunk = 4;
+
+// Takes the next chunk for the whole workgroup; every wave leaves the previous
 // tile (and its LDS) before the new index is published.
 __device__ __forceinline__ int batch_next(int* counter, int* s_tile) {
     __syncthreads();
-    if (threadIdx.x == 0) *s_tile = atomicAdd(counter, 1);
+    if (threadIdx.x == 0) *s_tile = atomicAdd(counter, kBatchChunk);
     __syncthreads();
     return *s_tile;
 }
@@ -59,17 +64,24 @@ __global__ __launch_bounds__(64 * WPG) void k_dcds_batch(const BatchTable* __res
     extern __shared__ uint32_t smem[];
     __shared__ int s_tile;
     const int total = tab->total_tiles;
+    const int n = tab->n_jobs;
     for (;;) {
-        const int t = batch_next(counter, &s_tile);
-        if (t >= total) break;
-        const BatchJob& jb = tab->jobs[batch_job_of(tab, t)];
-        int r = t - jb.tile_begin;
-        const int tx = r % jb.a.tiles_x;
-        r /= jb.a.tiles_x;
-        const int ty = r % jb.a.tiles_y;
-        const int pair = r / jb.a.tiles_y;
-        dcds_tile<B, RPL, WPG, RMAX>(smem, jb.a, jb.flags, pair, tx, ty, jb.start, jb.orient, jb.mv, jb.sad,
-                                     jb.nsp);
+        const int t0 = batch_next(counter, &s_tile);
+        if (t0 >= total) break;
+        int j = batch_job_of(tab, t0);
+        const int t1 = min(t0 + kBatchChunk, total);
+        for (int t = t0; t < t1; ++t) {
+            while (j + 1 < n && tab->jobs[j + 1].tile_begin <= t) ++j;
+            const BatchJob& jb = tab->jobs[j];
+            int r = t - jb.tile_begin;
+            const int tx = r % jb.a.tiles_x;
+            r /= jb.a.tiles_x;
+            const int ty = r % jb.a.tiles_y;
+            const int pair = r / jb.a.tiles_y;
+            if (t != t0) __syncthreads();  // the previous tile's waves are done with LDS
+            dcds_tile<B, RPL, WPG, RMAX>(smem, jb.a, jb.flags, pair, tx, ty, jb.start, jb.orient, jb.mv, jb.sad,
+                                         jb.nsp);
+        }
     }
 }
 
@@ -78,16 +90,23 @@ __global__ __launch_bounds__(256) void k_fs_batch(const BatchTable* __restrict__
     extern __shared__ uint32_t smem[];
     __shared__ int s_tile;
     const int total = tab->total_tiles;
+    const int n = tab->n_jobs;
     for (;;) {
-        const int t = batch_next(counter, &s_tile);
-        if (t >= total) break;
-        const BatchJob& jb = tab->jobs[batch_job_of(tab, t)];
-        int r = t - jb.tile_begin;
-        const int bx = r % jb.a.bw;
-        r /= jb.a.bw;
-        const int by = r % jb.a.bh;
-        const int pair = r / jb.a.bh;
-        fs_block<B>(smem, jb.a, pair, bx, by, jb.mv, jb.sad, jb.nsp);
+        const int t0 = batch_next(counter, &s_tile);
+        if (t0 >= total) break;
+        int j = batch_job_of(tab, t0);
+        const int t1 = min(t0 + kBatchChunk, total);
+        for (int t = t0; t < t1; ++t) {
+            while (j + 1 < n && tab->jobs[j + 1].tile_begin <= t) ++j;
+            const BatchJob& jb = tab->jobs[j];
+            int r = t - jb.tile_begin;
+            const int bx = r % jb.a.bw;
+            r /= jb.a.bw;
+            const int by = r % jb.a.bh;
+            const int pair = r / jb.a.bh;
+            if (t != t0) __syncthreads();
+            fs_block<B>(smem, jb.a, pair, bx, by, jb.mv, jb.sad, jb.nsp);
+        }
     }
 }
 
