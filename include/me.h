@@ -190,6 +190,61 @@ int me_autotune(const me_job *jobs, int32_t n_jobs, int32_t algo, int32_t block,
 int me_autotune_save(const char *path);
 int me_autotune_load(const char *path, int32_t *applied, int32_t *rejected);
 
+/*
+ * Learned start proposer (this library's addition, not the paper's method).
+ * A 4-layer convolutional network with bf16 storage and fp32 accumulation
+ * reads a 4x-downsampled pair: input channels (cur4 - ref4)/32 and
+ * (cur4 - 128)/64, where cur4, ref4 are 4x4 box means.  Layers: 3x3 conv
+ * 2->16 (ReLU), 3x3 stride 2 16->32 (ReLU), 3x3 stride 2 32->32 (ReLU), 3x3
+ * 32->3 (head u, v, o), all padded by 1, one head per 16x16 block.  Start
+ * vector = clamp(rint(8 u), rint(8 v)) to +-range; first cross vertical when
+ * o > 0.  Frames follow me_dcds (16x16 blocks).
+ *
+ * Parameters travel as one flat fp32 host vector of me_proposer_num_params()
+ * values: per layer W[ky][kx][ci][co] then bias[co].  Training minimises,
+ * averaged over blocks, huber(u - tx) + huber(v - ty) + 0.25 bce(o, |ty| >
+ * |tx|) with t = target vector / 8, by Adam (0.9, 0.999, 1e-8) on fp32 master
+ * weights.  Every reduction runs in a fixed order: repeated runs and resumed
+ * runs are bit-identical.
+ *
+ * A proposer belongs to the device current at creation.  Calls on one
+ * proposer must not overlap (they share its activation buffers, grown on
+ * demand with hipMalloc).  create/init/set/get synchronise the device; the
+ * others are stream-ordered.
+ */
+typedef struct me_proposer me_proposer;
+
+int32_t me_proposer_num_params(void);
+int me_proposer_create(me_proposer **out);                 /* all parameters 0             */
+int me_proposer_destroy(me_proposer *p);
+int me_proposer_init(me_proposer *p, uint64_t seed);       /* He-normal weights, 0 biases   */
+int me_proposer_set_weights(me_proposer *p, const float *host, int32_t n); /* EINVAL if not finite */
+int me_proposer_get_weights(me_proposer *p, float *host, int32_t n);
+int me_proposer_get_grads(me_proposer *p, float *host, int32_t n);          /* last backward */
+/* Adam moments (host, flat layout) and step count, for checkpoints.        */
+int me_proposer_get_state(me_proposer *p, float *m, float *v, int64_t *step, int32_t n);
+int me_proposer_set_state(me_proposer *p, const float *m, const float *v, int64_t step, int32_t n);
+/* head: device fp32 [n_pairs][height/16][width/16][3].                      */
+int me_proposer_forward(me_proposer *p, const uint8_t *cur, const uint8_t *ref, int32_t width, int32_t height,
+                        int32_t pitch, int64_t pair_stride, int32_t n_pairs, float *head, void *stream);
+/* Parameter gradients (me_proposer_get_grads) for a head gradient of the
+ * same shape (device fp32), through the activations of the last forward.  */
+int me_proposer_backward(me_proposer *p, const float *dhead, void *stream);
+/* One Adam step on the loss above; target: device FS vectors, one per block;
+ * loss: device float receiving the mean loss before the step.             */
+int me_proposer_train_step(me_proposer *p, const uint8_t *cur, const uint8_t *ref, int32_t width, int32_t height,
+                           int32_t pitch, int64_t pair_stride, int32_t n_pairs, const me_mv *target, float lr,
+                           float *loss, void *stream);
+/* Proposals: start (device, one per block) and orient (device bytes).     */
+int me_proposer_infer(me_proposer *p, const uint8_t *cur, const uint8_t *ref, int32_t width, int32_t height,
+                      int32_t pitch, int64_t pair_stride, int32_t n_pairs, int32_t range, me_mv *start,
+                      uint8_t *orient, void *stream);
+/* DCDS (16x16 blocks) from the proposer's starts with me_dcds_ex's fallback
+ * rule; p == NULL runs plain DCDS.                                          */
+int me_dcds_learned(me_proposer *p, const uint8_t *cur, const uint8_t *ref, int32_t width, int32_t height,
+                    int32_t pitch, int64_t pair_stride, int32_t n_pairs, int32_t range, int32_t algo, me_mv *mv,
+                    uint32_t *sad, uint32_t *nsp, void *stream);
+
 /* Releases the library's device and pinned buffers, graphs and streams (no
  * batch may be in flight).  Later calls allocate them again.               */
 int me_shutdown(void);

@@ -41,6 +41,20 @@ EXPORTS = [
     "me_autotune_save",
     "me_autotune_load",
     "me_shutdown",
+    "me_proposer_num_params",
+    "me_proposer_create",
+    "me_proposer_destroy",
+    "me_proposer_init",
+    "me_proposer_set_weights",
+    "me_proposer_get_weights",
+    "me_proposer_get_grads",
+    "me_proposer_get_state",
+    "me_proposer_set_state",
+    "me_proposer_forward",
+    "me_proposer_backward",
+    "me_proposer_train_step",
+    "me_proposer_infer",
+    "me_dcds_learned",
 ]
 
 MAX_JOBS = 4096
@@ -103,6 +117,32 @@ def lib() -> ctypes.CDLL:
         L.me_autotune_load.restype = ctypes.c_int
         L.me_shutdown.argtypes = []
         L.me_shutdown.restype = ctypes.c_int
+        fp = ctypes.POINTER(ctypes.c_float)
+        L.me_proposer_num_params.argtypes = []
+        L.me_proposer_num_params.restype = i32
+        L.me_proposer_create.argtypes = [ctypes.POINTER(vp)]
+        L.me_proposer_create.restype = ctypes.c_int
+        L.me_proposer_destroy.argtypes = [vp]
+        L.me_proposer_destroy.restype = ctypes.c_int
+        L.me_proposer_init.argtypes = [vp, ctypes.c_uint64]
+        L.me_proposer_init.restype = ctypes.c_int
+        for name in ("me_proposer_set_weights", "me_proposer_get_weights", "me_proposer_get_grads"):
+            getattr(L, name).argtypes = [vp, fp, i32]
+            getattr(L, name).restype = ctypes.c_int
+        L.me_proposer_get_state.argtypes = [vp, fp, fp, ctypes.POINTER(i64), i32]
+        L.me_proposer_get_state.restype = ctypes.c_int
+        L.me_proposer_set_state.argtypes = [vp, fp, fp, i64, i32]
+        L.me_proposer_set_state.restype = ctypes.c_int
+        L.me_proposer_forward.argtypes = [vp] + frame[:7] + [vp, vp]
+        L.me_proposer_forward.restype = ctypes.c_int
+        L.me_proposer_backward.argtypes = [vp, vp, vp]
+        L.me_proposer_backward.restype = ctypes.c_int
+        L.me_proposer_train_step.argtypes = [vp] + frame[:7] + [vp, ctypes.c_float, vp, vp]
+        L.me_proposer_train_step.restype = ctypes.c_int
+        L.me_proposer_infer.argtypes = [vp] + frame[:7] + [i32, vp, vp, vp]
+        L.me_proposer_infer.restype = ctypes.c_int
+        L.me_dcds_learned.argtypes = [vp] + frame[:7] + [i32, i32, vp, vp, vp, vp]
+        L.me_dcds_learned.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -290,6 +330,110 @@ def autotune(pairs, block=16, range_=15, algo=ME_ALGO_DCDS, reps=5, stream=None)
     rc, cfg, ms = me_autotune(jobs, len(pairs), algo, block, range_, reps, _stream(stream))
     _check(rc, "me_autotune")
     return cfg, ms
+
+
+class Proposer:
+    """Learned start proposer (bf16 CNN) living on the current GPU."""
+
+    def __init__(self, seed=None):
+        h = ctypes.c_void_p()
+        _check(lib().me_proposer_create(ctypes.byref(h)), "me_proposer_create")
+        self.h = h
+        self.n = lib().me_proposer_num_params()
+        if seed is not None:
+            _check(lib().me_proposer_init(self.h, seed), "me_proposer_init")
+
+    def close(self):
+        if self.h:
+            lib().me_proposer_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _fp(self, a):
+        return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+    def set_weights(self, w):
+        import numpy as np
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        _check(lib().me_proposer_set_weights(self.h, self._fp(w), len(w)), "me_proposer_set_weights")
+
+    def get_weights(self):
+        import numpy as np
+        w = np.zeros(self.n, np.float32)
+        _check(lib().me_proposer_get_weights(self.h, self._fp(w), self.n), "me_proposer_get_weights")
+        return w
+
+    def get_grads(self):
+        import numpy as np
+        g = np.zeros(self.n, np.float32)
+        _check(lib().me_proposer_get_grads(self.h, self._fp(g), self.n), "me_proposer_get_grads")
+        return g
+
+    def get_state(self):
+        import numpy as np
+        m = np.zeros(self.n, np.float32)
+        v = np.zeros(self.n, np.float32)
+        step = ctypes.c_int64(0)
+        _check(lib().me_proposer_get_state(self.h, self._fp(m), self._fp(v), ctypes.byref(step), self.n),
+               "me_proposer_get_state")
+        return m, v, step.value
+
+    def set_state(self, m, v, step):
+        import numpy as np
+        m = np.ascontiguousarray(m, dtype=np.float32)
+        v = np.ascontiguousarray(v, dtype=np.float32)
+        _check(lib().me_proposer_set_state(self.h, self._fp(m), self._fp(v), int(step), self.n),
+               "me_proposer_set_state")
+
+    def forward(self, cur, ref, stream=None):
+        torch = _torch()
+        P, H, W, pitch, stride = _frames(cur, ref)
+        head = torch.empty((P, H // 16, W // 16, 3), dtype=torch.float32, device=cur.device)
+        rc = lib().me_proposer_forward(self.h, cur.data_ptr(), ref.data_ptr(), W, H, pitch, stride, P,
+                                       head.data_ptr(), _stream(stream))
+        _check(rc, "me_proposer_forward")
+        return head
+
+    def backward(self, dhead, stream=None):
+        dhead = dhead.contiguous()
+        _check(lib().me_proposer_backward(self.h, dhead.data_ptr(), _stream(stream)), "me_proposer_backward")
+
+    def train_step(self, cur, ref, target, lr, stream=None):
+        """One Adam step; returns the (device) loss tensor before the step."""
+        torch = _torch()
+        P, H, W, pitch, stride = _frames(cur, ref)
+        loss = torch.empty((1,), dtype=torch.float32, device=cur.device)
+        target = target.contiguous()
+        rc = lib().me_proposer_train_step(self.h, cur.data_ptr(), ref.data_ptr(), W, H, pitch, stride, P,
+                                          target.data_ptr(), float(lr), loss.data_ptr(), _stream(stream))
+        _check(rc, "me_proposer_train_step")
+        return loss
+
+    def infer(self, cur, ref, range_, stream=None):
+        torch = _torch()
+        P, H, W, pitch, stride = _frames(cur, ref)
+        start = torch.empty((P, H // 16, W // 16, 2), dtype=torch.int16, device=cur.device)
+        orient = torch.empty((P, H // 16, W // 16), dtype=torch.uint8, device=cur.device)
+        rc = lib().me_proposer_infer(self.h, cur.data_ptr(), ref.data_ptr(), W, H, pitch, stride, P, range_,
+                                     start.data_ptr(), orient.data_ptr(), _stream(stream))
+        _check(rc, "me_proposer_infer")
+        return start, orient
+
+
+def dcds_learned(proposer, cur, ref, range_=31, algo=ME_ALGO_DCDS, out=None, stream=None):
+    """DCDS on 16x16 blocks from the proposer's starts (None: plain DCDS)."""
+    P, H, W, pitch, stride = _frames(cur, ref)
+    mv, sad, nsp = _outputs(P, H // 16, W // 16, cur.device, out)
+    h = proposer.h if proposer is not None else None
+    rc = lib().me_dcds_learned(h, cur.data_ptr(), ref.data_ptr(), W, H, pitch, stride, P, range_, algo,
+                               mv.data_ptr(), sad.data_ptr(), nsp.data_ptr(), _stream(stream))
+    _check(rc, "me_dcds_learned")
+    return mv, sad, nsp
 
 
 def dcds_surface(cost, valid=None, algo=ME_ALGO_DCDS, start=None, orient=None, stream=None):

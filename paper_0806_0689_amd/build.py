@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libme.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["me_api.hip", "me_batch.hip"]
+SOURCES = ["me_api.hip", "me_batch.hip", "me_proposer.hip"]
 FLAGS = [
     "--offload-arch=gfx950",
     "-O3",

@@ -164,3 +164,13 @@ def test_autotune_argument_checks(tmp_path):
     assert rc == me.ME_OK and rejected == 3 and applied == 0
     assert me.me_autotune_save(str(tmp_path / "out.txt")) == me.ME_OK
     assert (tmp_path / "out.txt").read_text().startswith("# me autotune cache v1")
+
+
+def test_proposer_host_checks():
+    from oracle import cnn
+    assert me.lib().me_proposer_num_params() == cnn.num_params()
+    assert me.lib().me_proposer_create(None) == me.ME_EINVAL
+    assert me.lib().me_proposer_destroy(None) == me.ME_OK
+    assert me.lib().me_proposer_init(None, 1) == me.ME_EINVAL
+    assert me.lib().me_proposer_forward(None, P, P, 64, 32, 64, 2048, 1, P, None) == me.ME_EINVAL
+    assert me.lib().me_proposer_backward(None, P, None) == me.ME_EINVAL
