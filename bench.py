@@ -128,13 +128,64 @@ def batch_leg(me, torch, dev, args):
     return res
 
 
+def learned_leg(me, torch, cur, ref, R, steps, warmup, fs_sad=None, plain=None):
+    """Learned-start DCDS (proposer inference + seeded DCDS, timed together)."""
+    from paper_0806_0689_amd.train import DEFAULT_WEIGHTS, load_proposer
+    p = load_proposer()
+    if p is None:
+        return {"status": "no trained checkpoint at %s" % DEFAULT_WEIGHTS}
+    fn = lambda: me.dcds_learned(p, cur, ref, R)  # noqa: E731
+    mv, sad, nsp = fn()
+    _, ms, _ = time_launches(fn, steps, warmup, torch)
+    _, ms_cnn, _ = time_launches(lambda: p.infer(cur, ref, R), steps, warmup, torch)
+    blocks = sad.numel()
+    res = {"mb_per_s": blocks / (ms * 1e-3), "ms_per_step": ms, "proposer_ms": ms_cnn,
+           "nsp_mean": float(nsp.double().mean()), "sad_mean": float(sad.double().mean())}
+    if fs_sad:
+        res["sad_over_fs"] = res["sad_mean"] / fs_sad
+    if plain:
+        res["sad_over_plain_dcds"] = res["sad_mean"] / plain["sad_mean"]
+        res["nsp_over_plain_dcds"] = res["nsp_mean"] / plain["nsp_mean"]
+    print("# learned: %.4f ms/step (proposer %.4f ms), %.3g MB/s, nsp %.3f, sad %.1f" % (
+        ms, ms_cnn, res["mb_per_s"], res["nsp_mean"], res["sad_mean"]), file=sys.stderr, flush=True)
+    return res
+
+
+def config5_leg(me, torch, dev, args):
+    """3840x2160, 60 frames, +-31, 16x16: plain DCDS, learned-start DCDS and FS."""
+    from synth import make_config
+    t0 = time.perf_counter()
+    seq = torch.from_numpy(make_config(5)).to(dev)
+    print("# generated 3840x2160 x 60 in %.1f s" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
+    cur, ref = seq[1:], seq[:-1]
+    steps = max(3, min(args.steps, 10))
+    out = {"workload": "3840x2160 uint8, 60 frames (59 pairs), 16x16, +-31"}
+    fn = lambda: me.fullsearch(cur, ref, 16, 31)  # noqa: E731
+    _, fs_sad, fs_nsp = fn()
+    _, ms_fs, _ = time_launches(fn, 3, 1, torch)
+    blocks = fs_sad.numel()
+    out["fs"] = {"mb_per_s": blocks / (ms_fs * 1e-3), "ms_per_step": ms_fs, "sad_mean": float(fs_sad.double().mean()),
+                 "nsp_mean": float(fs_nsp.double().mean())}
+    fn = lambda: me.dcds(cur, ref, 16, 31)  # noqa: E731
+    _, sad, nsp = fn()
+    _, ms, _ = time_launches(fn, steps, args.warmup, torch)
+    out["dcds"] = {"mb_per_s": blocks / (ms * 1e-3), "ms_per_step": ms, "sad_mean": float(sad.double().mean()),
+                   "nsp_mean": float(nsp.double().mean())}
+    out["dcds"]["sad_over_fs"] = out["dcds"]["sad_mean"] / out["fs"]["sad_mean"]
+    out["dcds_learned"] = learned_leg(me, torch, cur, ref, 31, steps, args.warmup, out["fs"]["sad_mean"],
+                                      out["dcds"])
+    print("# config5: fs %.3f ms, dcds %.4f ms" % (ms_fs, ms), file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", default="", help="comma list of extra legs to run (fs,dcds8,dcds_s,batch); dcds always runs")
+    ap.add_argument("--only", default="",
+                    help="comma list of extra legs to run (fs,dcds8,dcds_s,learned,batch,4k); dcds always runs")
     ap.add_argument("--sweep", action="store_true",
                     help="time every DCDS kernel configuration (rows per lane x waves per group) and exit")
     ap.add_argument("--calib-copy", action="store_true",
@@ -158,7 +209,7 @@ def main():
     seq = torch.from_numpy(seq_np).to(dev)
     cur, ref = seq[1:], seq[:-1]
     P = FRAMES - 1
-    legs = set(args.only.split(",")) if args.only else {"dcds", "fs", "dcds8", "dcds_s", "batch"}
+    legs = set(args.only.split(",")) if args.only else {"dcds", "fs", "dcds8", "dcds_s", "learned", "batch", "4k"}
     if args.calib_copy:
         src = torch.ones(256 << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -210,8 +261,16 @@ def main():
         leg("dcds8", lambda: me.dcds(cur, ref, 8, RANGE), args.steps, blocks8)
     if "dcds_s" in legs:
         leg("dcds_s", lambda: me.dcds(cur, ref, 16, RANGE, algo=me.ME_ALGO_DCDS_S), args.steps, blocks16)
+    if "learned" in legs:
+        fs_mean = results["fs"]["sad_mean"] if "fs" in results else None
+        results["dcds_learned"] = learned_leg(me, torch, cur, ref, RANGE, args.steps, args.warmup, fs_mean,
+                                              results["dcds"])
     if "batch" in legs:
         results["batch"] = batch_leg(me, torch, dev, args)
+    extra = {}
+    if "4k" in legs:
+        del seq, cur, ref
+        extra["config_4k_r31"] = config5_leg(me, torch, dev, args)
     if "fs" in legs:
         fs_sad = results["fs"]["sad_mean"]
         for k in ("dcds", "dcds_s"):
@@ -242,6 +301,7 @@ def main():
             "generator": "synth config 3, seed 3",
         },
         "algos": results,
+        **extra,
         "roofline": {
             "kernel": "k_dcds<16,%d,%d,15>" % me.me_get_config(16, RANGE),
             "bound": "hbm",
