@@ -194,12 +194,16 @@ ME_EXPORT int me_fullsearch(const uint8_t* cur, const uint8_t* ref, int32_t widt
     const FrameArgs a = frame_args(cur, ref, width, height, pitch, pair_stride, block, range, 1, 1);
     const long long grid = (long long)a.bw * a.bh * n_pairs;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    if (block == 16)
-        hipLaunchKernelGGL(k_fs<16>, dim3((unsigned)grid), dim3(256), fs_lds_bytes<16>(range), st, a,
-                           reinterpret_cast<int16_t*>(mv), sad, nsp);
-    else
-        hipLaunchKernelGGL(k_fs<8>, dim3((unsigned)grid), dim3(256), fs_lds_bytes<8>(range), st, a,
-                           reinterpret_cast<int16_t*>(mv), sad, nsp);
+    const int nt = fs_threads(range);
+    const bool j4 = fs_rows_per_item(range) == 4;
+    int16_t* mvp = reinterpret_cast<int16_t*>(mv);
+    if (block == 16) {
+        if (j4) hipLaunchKernelGGL((k_fs<16, 4>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<16>(range), st, a, mvp, sad, nsp);
+        else hipLaunchKernelGGL((k_fs<16, 1>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<16>(range), st, a, mvp, sad, nsp);
+    } else {
+        if (j4) hipLaunchKernelGGL((k_fs<8, 4>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<8>(range), st, a, mvp, sad, nsp);
+        else hipLaunchKernelGGL((k_fs<8, 1>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<8>(range), st, a, mvp, sad, nsp);
+    }
     return launched();
 }
 

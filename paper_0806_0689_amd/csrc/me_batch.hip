@@ -33,7 +33,8 @@ constexpr int kSlots = 2;
 
 enum { KIND_DCDS = 1, KIND_FS = 2 };
 
-using GraphKey = std::tuple<int, int, int, int, int, size_t, int>;  // kind, B, rpl, wpg, rmax, lds, cap
+// kind, B, rpl, wpg, range class, kernel, threads, lds, cap: everything a captured graph bakes in.
+using GraphKey = std::tuple<int, int, int, int, int, const void*, int, size_t, int>;
 
 struct Slot {
     BatchTable* host = nullptr;  // pinned
@@ -127,9 +128,12 @@ Variant dcds_variant_r(int rpl, int wpg, int R) {
 Variant pick_variant(int kind, int B, int rpl, int wpg, int R) {
     if (kind == KIND_FS) {
         const size_t lds = (B == 16 ? fs_lds_bytes<16>(R) : fs_lds_bytes<8>(R)) + 16;
-        return Variant{B == 16 ? reinterpret_cast<const void*>(&k_fs_batch<16>)
-                               : reinterpret_cast<const void*>(&k_fs_batch<8>),
-                       256, lds};
+        const bool j4 = fs_rows_per_item(R) == 4;
+        const void* fn = B == 16 ? (j4 ? reinterpret_cast<const void*>(&k_fs_batch<16, 4>)
+                                       : reinterpret_cast<const void*>(&k_fs_batch<16, 1>))
+                                 : (j4 ? reinterpret_cast<const void*>(&k_fs_batch<8, 4>)
+                                       : reinterpret_cast<const void*>(&k_fs_batch<8, 1>));
+        return Variant{fn, fs_threads(R), lds};
     }
     const int rc = range_class(R);
     if (B == 16) {
@@ -220,7 +224,7 @@ int batch_launch(const me_job* jobs, int32_t n_jobs, int32_t algo, int32_t block
         return ME_EUNSUPPORTED;
     const unsigned grid = (unsigned)(per_cu * g_batch.cus);
 
-    const GraphKey key{kind, block, rpl, wpg, range_class(range), v.lds, cap};
+    const GraphKey key{kind, block, rpl, wpg, range_class(range), v.fn, v.threads, v.lds, cap};
     auto it = s.graphs.find(key);
     if (it == s.graphs.end()) {
         hipGraph_t graph = nullptr;

@@ -22,77 +22,125 @@ __device__ __forceinline__ void stage_window(uint32_t* dst, const uint8_t* frame
 }
 
 // ---------------------------------------------------------------------------
-// Full search.  One workgroup per block.  Work item (y, g): candidate row y
-// and four horizontally adjacent candidates x = x_g .. x_g + 3, all four
-// evaluated at once by v_qsad_pk_u16_u8 on an 8-byte reference window
-// against each 4-byte current word.
+// Full search.  One workgroup per block.  Work item (y-group, g): J
+// consecutive candidate rows y and four horizontally adjacent candidates
+// x = x_g .. x_g + 3; v_qsad_pk_u16_u8 evaluates the four x at once on an
+// 8-byte reference window against each 4-byte current word, and each
+// reference row read from LDS serves the J rows it belongs to.  The current
+// block is wave-uniform (scalar loads).
 // Key of a candidate: SAD << 13 | (|x|+|y|) << 7 | (y + 31) << 1 | (x > 0),
 // whose minimum is the tie order (SAD, |x|+|y|, y, x).
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int fs_groups(int R) { return margin_words(R) + (R + 1 + 3) / 4; }
 __host__ __device__ constexpr int fs_window_words(int B, int R) { return fs_groups(R) + B / 4; }
+__host__ __device__ constexpr int fs_rows_per_item(int R) { return R <= 7 ? 1 : 4; }
+__host__ __device__ constexpr int fs_items(int R) {
+    return fs_groups(R) * ((2 * R + 1 + fs_rows_per_item(R) - 1) / fs_rows_per_item(R));
+}
+__host__ __device__ constexpr int fs_threads(int R) {
+    return fs_items(R) <= 64 ? 64 : (fs_items(R) <= 128 ? 128 : 256);
+}
 template <int B>
 __host__ __device__ constexpr size_t fs_lds_bytes(int R) {
-    return (size_t)4 * ((B + 2 * R) * fs_window_words(B, R)) + (size_t)B * B + 4 * 4;
+    const int J = fs_rows_per_item(R);
+    const int rows = ((2 * R + 1 + J - 1) / J) * J + B - 1;
+    return (size_t)4 * rows * fs_window_words(B, R) + 4 * 4;
 }
 
 __device__ __forceinline__ uint32_t fs_key(uint32_t s, int x, int y) {
     return (s << 13) | ((uint32_t)(abs(x) + abs(y)) << 7) | ((uint32_t)(y + 31) << 1) | (x > 0 ? 1u : 0u);
 }
 
-// One block of one frame pair; all 256 threads of the workgroup call it.
-template <int B>
+// J candidate rows per item; nt threads per workgroup.  The block rows are
+// taken V at a time (a runtime loop, so that only V rows of the current block
+// are live in scalar registers); each step reads the V + J - 1 reference rows
+// it needs from LDS.
+template <int B, int J>
+__device__ __forceinline__ uint32_t fs_items_min(const uint32_t* win, int WD, int G, int items, int R, int MW,
+                                                 const uint32_t* cur, int cpw, int lox, int hix, int loy, int hiy,
+                                                 int nt) {
+    constexpr int K = B / 4;
+    constexpr int V = 4;
+    constexpr int Q = V + J - 1;
+    uint32_t best = 0xFFFFFFFFu;
+    for (int it = threadIdx.x; it < items; it += nt) {
+        const int yg = it / G, g = it - yg * G;
+        const int y0 = yg * J;  // first candidate row index (y = y0 - R)
+        uint64_t acc[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) acc[j] = 0;
+#pragma unroll 1
+        for (int vb = 0; vb < B; vb += V) {
+            uint32_t c[V][K];
+#pragma unroll
+            for (int u = 0; u < V; ++u)
+#pragma unroll
+                for (int k = 0; k < K; ++k) c[u][k] = cur[(vb + u) * cpw + k];
+            uint32_t d[Q][K + 1];
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+#pragma unroll
+                for (int k = 0; k <= K; ++k) d[q][k] = win[(y0 + vb + q) * WD + g + k];
+#pragma unroll
+            for (int u = 0; u < V; ++u)
+#pragma unroll
+                for (int j = 0; j < J; ++j)
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+                        acc[j] = __builtin_amdgcn_qsad_pk_u16_u8(((uint64_t)d[u + j][k + 1] << 32) | d[u + j][k],
+                                                                 c[u][k], acc[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int y = y0 + j - R;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int x = -4 * MW + 4 * g + i;
+                const uint32_t s = (uint32_t)(acc[j] >> (16 * i)) & 0xFFFFu;
+                const bool ok = x >= lox && x <= hix && y >= loy && y <= hiy;
+                best = min(best, ok ? fs_key(s, x, y) : 0xFFFFFFFFu);
+            }
+        }
+    }
+    return best;
+}
+
+// One block of one frame pair; all nt threads of the workgroup call it.
+// J = fs_rows_per_item(R) (checked by the caller).
+template <int B, int J>
 __device__ __forceinline__ void fs_block(uint32_t* smem, const FrameArgs& a, int pair, int bx, int by,
                                          int16_t* __restrict__ mv, uint32_t* __restrict__ sad,
-                                         uint32_t* __restrict__ nsp) {
+                                         uint32_t* __restrict__ nsp, int nt) {
     const int R = a.R;
     const int MW = margin_words(R);
     const int G = fs_groups(R);
     const int WD = fs_window_words(B, R);
-    const int WR = B + 2 * R;
+    const int DG = (2 * R + 1 + J - 1) / J;
+    const int WR = DG * J + B - 1;
     uint32_t* win = smem;
-    uint32_t* curs = smem + WR * WD;
-    uint32_t* part = curs + B * B / 4;
+    uint32_t* part = smem + WR * WD;
 
     const uint8_t* curf = a.cur + (long long)pair * a.pair_stride;
     const uint8_t* reff = a.ref + (long long)pair * a.pair_stride;
     const int x0 = bx * B, y0 = by * B;
-    stage_window(win, reff, a.W, a.H, a.pitch, x0 - 4 * MW, y0 - R, WR, WD, threadIdx.x, 256);
-    stage_window(curs, curf, a.W, a.H, a.pitch, x0, y0, B, B / 4, threadIdx.x, 256);
+    stage_window(win, reff, a.W, a.H, a.pitch, x0 - 4 * MW, y0 - R, WR, WD, threadIdx.x, nt);
+    // The current block is read straight from global memory: the same words
+    // for every lane (scalar loads).
+    const uint32_t* cur = reinterpret_cast<const uint32_t*>(curf + (size_t)y0 * a.pitch + x0);
     __syncthreads();
 
     const int lox = max(-R, -x0), hix = min(R, a.W - B - x0);
     const int loy = max(-R, -y0), hiy = min(R, a.H - B - y0);
-    uint32_t best = 0xFFFFFFFFu;
-    const int items = (2 * R + 1) * G;
-    for (int it = threadIdx.x; it < items; it += 256) {
-        const int yi = it / G, g = it - yi * G;
-        const int y = yi - R;
-        uint64_t acc = 0;
-        for (int v = 0; v < B; ++v) {
-            const uint32_t* row = win + (yi + v) * WD + g;
-            uint32_t d[B / 4 + 1];
-#pragma unroll
-            for (int k = 0; k <= B / 4; ++k) d[k] = row[k];
-#pragma unroll
-            for (int k = 0; k < B / 4; ++k)
-                acc = __builtin_amdgcn_qsad_pk_u16_u8(((uint64_t)d[k + 1] << 32) | d[k], curs[v * (B / 4) + k], acc);
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int x = -4 * MW + 4 * g + i;
-            const uint32_t s = (uint32_t)(acc >> (16 * i)) & 0xFFFFu;
-            const bool ok = x >= lox && x <= hix && y >= loy && y <= hiy;
-            best = min(best, ok ? fs_key(s, x, y) : 0xFFFFFFFFu);
-        }
-    }
+    const int items = G * DG;
+    uint32_t best = fs_items_min<B, J>(win, WD, G, items, R, MW, cur, a.pitch / 4, lox, hix, loy, hiy, nt);
     // Workgroup minimum.
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) best = min(best, (uint32_t)__shfl_xor((int)best, o, 64));
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = best;
     __syncthreads();
     if (threadIdx.x == 0) {
-        const uint32_t k = min(min(part[0], part[1]), min(part[2], part[3]));
+        uint32_t k = part[0];
+        for (int w = 1; w < nt / 64; ++w) k = min(k, part[w]);
         const int sgn = (int)(k & 1u);
         const int y = (int)((k >> 1) & 63u) - 31;
         const int l1 = (int)((k >> 7) & 63u);
@@ -105,7 +153,7 @@ __device__ __forceinline__ void fs_block(uint32_t* smem, const FrameArgs& a, int
     }
 }
 
-template <int B>
+template <int B, int J>
 __global__ __launch_bounds__(256) void k_fs(FrameArgs a, int16_t* __restrict__ mv, uint32_t* __restrict__ sad,
                                             uint32_t* __restrict__ nsp) {
     extern __shared__ uint32_t smem[];
@@ -114,7 +162,7 @@ __global__ __launch_bounds__(256) void k_fs(FrameArgs a, int16_t* __restrict__ m
     t /= a.bw;
     const int by = t % a.bh;
     const int pair = t / a.bh;
-    fs_block<B>(smem, a, pair, bx, by, mv, sad, nsp);
+    fs_block<B, J>(smem, a, pair, bx, by, mv, sad, nsp, blockDim.x);
 }
 
 }  // namespace me
