@@ -43,8 +43,10 @@ struct DcdsGeo {
     static constexpr int ML = round_up(MR, 16);              // bytes left of the tile
     static constexpr int NEED = round_up(ML + TW + RMAX + 6, 16) / 4;  // words a row must hold
     // Row pitch of 32m + 1 words: the lanes of a block read consecutive rows
-    // at one column, and blocks sit 4 words apart, so a half-wave's 32 reads
-    // fall into distinct banks.
+    // at one column, so they fall into consecutive banks.  (Giving each lane
+    // adjacent rows would let one ds_read2 fetch both, but spreads a block
+    // over every other bank and nearly doubles the bank conflicts between
+    // the blocks of a wave.)
     static constexpr int WDW = (NEED + 30) / 32 * 32 + 1;
     static constexpr int WR = TH + 2 * MR;   // LDS rows
     static constexpr int WIN_WORDS = WR * WDW;
@@ -93,22 +95,24 @@ __device__ __forceinline__ void stage(uint32_t* win, const uint8_t* frame, int W
 }
 
 // Lane g of a block holds rows g, g + L, ..., g + (RPL - 1) L of the block.
+// A point's address is the LDS byte offset of its reference pixel for this
+// lane's first row: a00 + y * ROWB + x.
 template <int B, int RPL, int WDW>
 struct FrameEval {
     static constexpr int K = B / 4;
     static constexpr int L = B / RPL;
     static constexpr int ROWB = WDW * 4;
     static constexpr int JW = L * WDW;  // words between a lane's rows
-    const uint8_t* lds;  // window base
-    int base;            // LDS byte offset of (this lane's first row, block column 0) at offset (0, 0)
+    int a00;             // address of point (0, 0): an LDS byte address
     uint32_t cur[RPL][K];
 
-    // Partial SAD of point (x, y) over this lane's rows, added into the low
-    // (HI = false) or high (HI = true) half of acc.
+    __device__ __forceinline__ int row() const { return ROWB; }
+
+    // Partial SAD of the point at address a over this lane's rows, added into
+    // the low (HI = false) or high (HI = true) half of acc.
     template <bool HI>
-    __device__ __forceinline__ uint32_t pt(int x, int y, uint32_t acc) const {
-        const int a = __mul24(y, ROWB) + x + base;
-        const uint32_t* w = reinterpret_cast<const uint32_t*>(lds + (a & ~3));
+    __device__ __forceinline__ uint32_t pt(int a, uint32_t acc) const {
+        const lds_words w = lds_at((uint32_t)a & ~3u);
 #pragma unroll
         for (int j = 0; j < RPL; ++j) {
             uint32_t d[K + 1];
@@ -123,13 +127,15 @@ struct FrameEval {
         return acc;
     }
 
-    __device__ __forceinline__ void pair(int x0, int y0, int x1, int y1, uint32_t& c0, uint32_t& c1) const {
-        uint32_t acc = pt<false>(x0, y0, 0u);
-        acc = pt<true>(x1, y1, acc);
+    __device__ __forceinline__ void pair(int a0, int a1, uint32_t& c0, uint32_t& c1) const {
+        uint32_t acc = pt<false>(a0, 0u);
+        acc = pt<true>(a1, acc);
         acc = group_sum<L>(acc);
         c0 = acc & 0xFFFFu;
         c1 = acc >> 16;
     }
+
+    __device__ __forceinline__ uint32_t one(int a0) const { return group_sum<L>(pt<false>(a0, 0u)); }
 
     // HCSP at the origin: the centre row is read once (K + 2 words from 4
     // bytes left of the block), shifted by 2 bytes, and v_qsad_pk_u16_u8
@@ -138,7 +144,7 @@ struct FrameEval {
     __device__ __forceinline__ void cross0(uint32_t (&c)[7]) const {
         uint64_t q = 0;
         uint32_t s2 = 0, s3 = 0;
-        const uint32_t* w = reinterpret_cast<const uint32_t*>(lds + base - 4);
+        const lds_words w = lds_at((uint32_t)(a00 - 4));
 #pragma unroll
         for (int j = 0; j < RPL; ++j) {
             uint32_t d[K + 2], up[K], dn[K];
@@ -173,28 +179,14 @@ struct FrameEval {
         c[6] = s3;
     }
 
-    // The cross at any centre (learned start), t = vertical orientation.
-    __device__ __forceinline__ void cross(int cx, int cy, bool t, uint32_t (&c)[7]) const {
-        const int ax = t ? 0 : 1, ay = t ? 1 : 0;  // unit step along the long arm
-        uint32_t u;
-        pair(cx, cy, cx - ax, cy - ay, c[0], c[1]);
-        pair(cx + ax, cy + ay, cx - 2 * ax, cy - 2 * ay, c[2], c[3]);
-        pair(cx + 2 * ax, cy + 2 * ay, cx - ay, cy - ax, c[4], c[5]);
-        pair(cx + ay, cy + ax, cx, cy, c[6], u);
+    // The cross centred at address a, t = vertical orientation.
+    __device__ __forceinline__ void cross(int a, bool t, uint32_t (&c)[7]) const {
+        const int arm = t ? ROWB : 1, perp = t ? 1 : ROWB;
+        pair(a, a - arm, c[0], c[1]);
+        pair(a + arm, a - 2 * arm, c[2], c[3]);
+        pair(a + 2 * arm, a - perp, c[4], c[5]);
+        c[6] = one(a + perp);
     }
-
-    __device__ __forceinline__ void diamond(int cx, int cy, bool t, uint32_t (&c)[4]) const {
-        const int ax = t ? 0 : 1, ay = t ? 1 : 0;
-        pair(cx - 2 * ax, cy - 2 * ay, cx + 2 * ax, cy + 2 * ay, c[0], c[1]);
-        pair(cx - ay, cy - ax, cx + ay, cy + ax, c[2], c[3]);
-    }
-
-    __device__ __forceinline__ void mids(int cx, int cy, bool t, uint32_t (&c)[2]) const {
-        const int ax = t ? 0 : 1, ay = t ? 1 : 0;
-        pair(cx - ax, cy - ay, cx + ax, cy + ay, c[0], c[1]);
-    }
-
-    __device__ __forceinline__ void probe(int sx, int sy, uint32_t (&c)[2]) const { pair(0, 0, sx, sy, c[0], c[1]); }
 };
 
 // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
@@ -241,8 +233,7 @@ __device__ __forceinline__ void dcds_tile(uint32_t* smem, const FrameArgs& a, in
     for (int i = g; i < BMW; i += L) bm[i] = 0u;
 
     FrameEval<B, RPL, G::WDW> ev;
-    ev.lds = reinterpret_cast<const uint8_t*>(win);
-    ev.base = (G::MR + wave * B + g) * (G::WDW * 4) + G::ML + b * B;
+    ev.a00 = (int)lds_offset(win) + (G::MR + wave * B + g) * (G::WDW * 4) + G::ML + b * B;
     const int x0 = bx * B, y0 = by * B;
     if (exists) {
 #pragma unroll
@@ -260,8 +251,6 @@ __device__ __forceinline__ void dcds_tile(uint32_t* smem, const FrameArgs& a, in
             }
         }
     }
-    Roles<L> ro;
-    ro.init(g);
     __syncthreads();
     if (exists) {
         Bounds bd;
@@ -278,8 +267,9 @@ __device__ __forceinline__ void dcds_tile(uint32_t* smem, const FrameArgs& a, in
             sy = start[2 * idx + 1];
             ov = orient != nullptr && orient[idx] != 0;
         }
-        const SearchOut r =
-            dcds_search<L>(ev, R, bd, bm, ro, b * L, (flags & DCDS_SIMPLIFIED) != 0, seeded, sx, sy, ov);
+        const SearchOut r = (flags & DCDS_SIMPLIFIED) != 0
+                                ? dcds_search<L, true>(ev, R, bd, bm, g, seeded, sx, sy, ov)
+                                : dcds_search<L, false>(ev, R, bd, bm, g, seeded, sx, sy, ov);
         if (g == 0) {
             mv[2 * idx] = (int16_t)r.x;
             mv[2 * idx + 1] = (int16_t)r.y;

@@ -21,9 +21,11 @@ constexpr int DPP_ROR4 = 0x124;
 constexpr int DPP_ROR2 = 0x122;
 constexpr int DPP_ROR1 = 0x121;
 
+// Every control used here reads a lane of the same row, so bound_ctrl never
+// applies; setting it lets the move fold into the consuming add or min.
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp(uint32_t x) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xf, 0xf, false);
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xf, 0xf, true);
 }
 
 // Sum over aligned groups of L lanes (L = 4, 8 or 16); every lane of the group
@@ -66,6 +68,13 @@ __device__ __forceinline__ uint32_t group_min<16>(uint32_t x) {
     x = min(x, dpp<DPP_ROR2>(x));
     x = min(x, dpp<DPP_ROR1>(x));
     return x;
+}
+
+// LDS addressing by byte offset (a 32-bit LDS address, not a generic pointer).
+typedef const __attribute__((address_space(3))) uint32_t* lds_words;
+__device__ __forceinline__ lds_words lds_at(uint32_t byte) { return (lds_words)(uintptr_t)byte; }
+__device__ __forceinline__ uint32_t lds_offset(const void* p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
 }
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }

@@ -2,16 +2,21 @@
 // kernel.  One group of L lanes runs one search; every value below is uniform
 // across the group, and different groups of a wave diverge freely (EXEC masks).
 //
-// Each step evaluates the whole pattern, including points met before: a point
-// already in S has a distortion no smaller than the current centre (the
-// centre is the minimum of S by induction, since it only moves to a strictly
-// smaller value), and ties keep the centre, so recomputing such a point never
-// changes a decision.  The set S itself is kept as a bitmap in LDS, one bit
-// per window point, and only serves to count distinct points (NSP).
+// Visited points never win.  The centre is the minimum of every point met so
+// far (it only moves to a point of strictly smaller distortion, and ties keep
+// the centre), so a point evaluated before cannot beat it.  Two consequences
+// are used below:
+//  - each small-diamond step evaluates only its three new points: the distant
+//    point behind the centre (on the side it came from) is always a point of
+//    the previous pattern;
+//  - the set S of visited points only serves to count distinct points (NSP):
+//    it is a bitmap in LDS, one bit per window point, set (without reading
+//    it back) for every valid point evaluated, and NSP is its popcount.
+// The DCDS^S rule of Step 4 compares the two distant points of the final
+// diamond, so the cost of the one behind the centre is carried along.
 //
-// All pattern points lie on the two axes through the pattern centre.  The
-// horizontal patterns of §III-A are listed below as (offset along the arm, arm
-// index) pairs; the vertical ones are their transposes.
+// Points are (x, y) with the pattern's long arm along x for the horizontal
+// patterns (HCSP, HDSP) and along y for the vertical ones.
 #pragma once
 
 #include "me_device.hpp"
@@ -20,188 +25,190 @@ namespace me {
 
 enum { ALGO_FS = 0, ALGO_DCDS = 1, ALGO_DCDS_S = 2 };
 
-// Horizontal cross (HCSP), centre first: (0,0) (-1,0) (+1,0) (-2,0) (+2,0) (0,-1) (0,+1).
-__host__ __device__ constexpr int cross_x(int i) { return i == 1 ? -1 : i == 2 ? 1 : i == 3 ? -2 : i == 4 ? 2 : 0; }
-__host__ __device__ constexpr int cross_y(int i) { return i == 5 ? -1 : i == 6 ? 1 : 0; }
-// Horizontal diamond (HDSP) without its centre: distant (-2,0) (+2,0), near (0,-1) (0,+1).
-__host__ __device__ constexpr int diam_x(int i) { return i == 0 ? -2 : i == 1 ? 2 : 0; }
-__host__ __device__ constexpr int diam_y(int i) { return i == 2 ? -1 : i == 3 ? 1 : 0; }
-// Middle points of the horizontal diamond: (-1,0) (+1,0).
-__host__ __device__ constexpr int mid_x(int i) { return i == 0 ? -1 : 1; }
-
 struct Bounds {
     int lox, hix, loy, hiy;  // candidate set: lox <= x <= hix, loy <= y <= hiy
-    __device__ __forceinline__ bool inx(int x) const { return (unsigned)(x - lox) <= (unsigned)(hix - lox); }
-    __device__ __forceinline__ bool iny(int y) const { return (unsigned)(y - loy) <= (unsigned)(hiy - loy); }
-    __device__ __forceinline__ bool in(int x, int y) const { return inx(x) && iny(y); }
 };
-
-// Lane roles for NSP counting: lane g of a group marks point g (and g + L, ...)
-// of the pattern being evaluated.  Offsets are stored for the horizontal
-// orientation and transposed on use.
-template <int L>
-struct Roles {
-    static constexpr int NR = (7 + L - 1) / L;  // rounds needed for 7 points
-    int8_t cx[NR], cy[NR], dx[NR], dy[NR], mx[NR];
-    bool cv[NR], dv[NR], mv[NR];
-    __device__ __forceinline__ void init(int g) {
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            const int i = g + r * L;
-            cx[r] = (int8_t)(i == 1 ? -1 : i == 2 ? 1 : i == 3 ? -2 : i == 4 ? 2 : 0);
-            cy[r] = (int8_t)(i == 5 ? -1 : i == 6 ? 1 : 0);
-            cv[r] = i < 7;
-            dx[r] = (int8_t)(i == 0 ? -2 : i == 1 ? 2 : 0);
-            dy[r] = (int8_t)(i == 2 ? -1 : i == 3 ? 1 : 0);
-            dv[r] = i < 4;
-            mx[r] = (int8_t)(i == 0 ? -1 : 1);
-            mv[r] = i < 2;
-        }
-    }
-};
-
-// Marks one point per lane (when `act`) in the group's bitmap; returns the
-// number of points of the group that were not marked before.
-template <int L>
-__device__ __forceinline__ int mark(uint32_t* bm, int R, int gbase, bool act, int x, int y) {
-    bool fresh = false;
-    if (act) {
-        const int k = __mul24(y + R, 2 * R + 1) + (x + R);
-        const uint32_t bit = 1u << (k & 31);
-        const uint32_t old = atomicOr(&bm[k >> 5], bit);
-        fresh = (old & bit) == 0;
-    }
-    const uint64_t b = __builtin_amdgcn_ballot_w64(fresh);
-    const uint64_t m = (L == 64) ? ~0ull : ((1ull << L) - 1ull);
-    return __popcll((b >> gbase) & m);
-}
 
 struct SearchOut {
     int x, y;
     uint32_t cost, nsp;
 };
 
+// Room of a centre inside the candidate set: how far it may move towards
+// -x, +x, -y, +y.  A point at distance d along one axis is valid iff the room
+// on that side is at least d.
+struct Room {
+    int xl, xh, yl, yh;
+    __device__ __forceinline__ void at(const Bounds& bd, int cx, int cy) {
+        xl = cx - bd.lox;
+        xh = bd.hix - cx;
+        yl = cy - bd.loy;
+        yh = bd.hiy - cy;
+    }
+    // Along the arm (x unless t) and across it.
+    __device__ __forceinline__ int am(bool t) const { return t ? yl : xl; }
+    __device__ __forceinline__ int ap(bool t) const { return t ? yh : xh; }
+    __device__ __forceinline__ int pm(bool t) const { return t ? xl : yl; }
+    __device__ __forceinline__ int pp(bool t) const { return t ? xh : yh; }
+};
+
 __device__ __forceinline__ uint32_t key(bool valid, uint32_t cost, uint32_t idx) {
     return valid ? ((cost << 3) | idx) : 0xFFFFFFFFu;
 }
 
-// Ev provides, for the group (all costs uniform over the group, each < 2^28):
-//   cross0(c[7])               HCSP at the origin (the paper's Step 1)
-//   cross(cx, cy, vert, c[7])  the cross at any centre (learned start)
-//   diamond(cx, cy, vert, c[4])
-//   mids(cx, cy, vert, c[2])
-//   probe(sx, sy, c[2])        origin and one start point
+// Ev (all costs uniform over the group, each < 2^28).  A point is named by an
+// address that is affine in (x, y): a(x, y) = a00 + y * row() + x.
+//   cross0(c[7])              HCSP at the origin (Step 1)
+//   cross(a, t, c[7])         the cross centred at address a; t = vertical
+//   pair(a0, a1, c0, c1)      two points
+//   one(a0)                   one point
+// HCSP order: centre, -1, +1, -2, +2 along the arm, -1, +1 across it.
 // Points outside the candidate set may be evaluated on any finite data; their
 // results are masked here.
-// simplified: DCDS^S Step 4; seeded: learned start (sx, sy, orient_v).
-template <int L, class Ev>
-__device__ SearchOut dcds_search(const Ev& ev, int R, const Bounds& bd, uint32_t* bm, const Roles<L>& ro, int gbase,
-                                 bool simplified, bool seeded, int sx, int sy, bool orient_v) {
-    constexpr int NR = Roles<L>::NR;
-    int nsp = 0;
+// simplified: Step 4 of DCDS^S; seeded: learned start (sx, sy, orient_v).
+template <int L, bool SIMPLIFIED, class Ev>
+__device__ SearchOut dcds_search(const Ev& ev, int R, const Bounds& bd, uint32_t* bm, int g, bool seeded, int sx,
+                                 int sy, bool orient_v) {
+    static_assert(L == 4 || L == 8 || L == 16, "group of 4, 8 or 16 lanes");
+    const int S = 2 * R + 1;      // bitmap row length
+    const int k00 = R * S + R;    // bitmap index of the origin
+    const int rs = ev.row();
     int cx = 0, cy = 0;
-    bool t = false;  // current pattern is vertical
+    bool t = false;               // current pattern is vertical
+
+    auto mark = [&](bool act, int k) {
+        if (act) (void)atomicOr(&bm[k >> 5], 1u << (k & 31));
+    };
+    // NSP: the number of bits set (the group's own LDS operations complete in
+    // order, so every mark is visible here).
+    auto count = [&]() -> uint32_t {
+        uint32_t n = 0;
+        for (int i = g; i < (S * S + 31) / 32; i += L) n += __popc(bm[i]);
+        return group_sum<L>(n);
+    };
 
     uint32_t c7[7];
     if (seeded) {
-        // Learned start: probe the origin and the (clamped) start.
+        // Learned start: probe the origin and the (clamped) start; lane 0
+        // marks the origin, lane 1 the start.
         sx = clampi(sx, bd.lox, bd.hix);
         sy = clampi(sy, bd.loy, bd.hiy);
         const bool moved = (sx != 0) || (sy != 0);
-        uint32_t pc[2];
-        ev.probe(sx, sy, pc);
-        // Lane 0 of the group marks the origin, lane 1 the start.
-        const bool is_start = ro.mx[0] > 0;
-        nsp += mark<L>(bm, R, gbase, ro.mv[0] && (!is_start || moved), is_start ? sx : 0, is_start ? sy : 0);
-        if (moved && pc[1] < pc[0]) {
+        uint32_t p0, ps;
+        ev.pair(ev.a00, ev.a00 + __mul24(sy, rs) + sx, p0, ps);
+        mark(g == 0 || (g == 1 && moved), k00 + (g == 1 ? __mul24(sy, S) + sx : 0));
+        if (moved && ps < p0) {
             cx = sx;
             cy = sy;
             t = orient_v;
         }
-        ev.cross(cx, cy, t, c7);
+        ev.cross(ev.a00 + __mul24(cy, rs) + cx, t, c7);
     } else {
         ev.cross0(c7);
     }
 
     // Step 1: the cross centred at (cx, cy).
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const int ox = t ? ro.cy[r] : ro.cx[r], oy = t ? ro.cx[r] : ro.cy[r];
-        const int x = cx + ox, y = cy + oy;
-        nsp += mark<L>(bm, R, gbase, ro.cv[r] && bd.in(x, y), x, y);
-    }
-    uint32_t km;
+    Room rc;
+    rc.at(bd, cx, cy);
+    const bool am1 = rc.am(t) >= 1, ap1 = rc.ap(t) >= 1, am2 = rc.am(t) >= 2, ap2 = rc.ap(t) >= 2;
+    const bool pm1 = rc.pm(t) >= 1, pp1 = rc.pp(t) >= 1;
     {
-        uint32_t m = key(true, c7[0], 0);
+        // Lane g marks cross point g (and g + L when L = 4).
 #pragma unroll
-        for (int i = 1; i < 7; ++i) {
-            // Points 1-4 lie on the cross's long arm, 5-6 on the short one.
-            const int o = i <= 4 ? cross_x(i) : cross_y(i);
-            const bool along_x = (i <= 4) != t;
-            const bool v = along_x ? bd.inx(cx + o) : bd.iny(cy + o);
-            m = min(m, key(v, c7[i], (uint32_t)i));
+        for (int r = 0; r < (7 + L - 1) / L; ++r) {
+            const int i = g + r * L;
+            const int oa = i == 1 ? -1 : i == 2 ? 1 : i == 3 ? -2 : i == 4 ? 2 : 0;  // along the arm
+            const int op = i == 5 ? -1 : i == 6 ? 1 : 0;                             // across it
+            const bool v = i == 0 || (i == 1 && am1) || (i == 2 && ap1) || (i == 3 && am2) || (i == 4 && ap2) ||
+                           (i == 5 && pm1) || (i == 6 && pp1);
+            const int dx = t ? op : oa, dy = t ? oa : op;
+            mark(v, k00 + __mul24(cy + dy, S) + (cx + dx));
         }
-        km = m;
     }
-    const int w = (int)(km & 7u);
-    if (w == 0) return SearchOut{cx, cy, km >> 3, (uint32_t)nsp};  // half-way stop
+    uint32_t m = c7[0] << 3;
+    m = min(m, key(am1, c7[1], 1u));
+    m = min(m, key(ap1, c7[2], 2u));
+    m = min(m, key(am2, c7[3], 3u));
+    m = min(m, key(ap2, c7[4], 4u));
+    m = min(m, key(pm1, c7[5], 5u));
+    m = min(m, key(pp1, c7[6], 6u));
+    const uint32_t w = m & 7u;
+    if (w == 0) return SearchOut{cx, cy, m >> 3, count()};  // half-way stop
+
+    // Move to the BMP.  Switching strategy one: a BMP along x selects the
+    // horizontal diamond, otherwise the vertical one.  dir: the last move
+    // (its sign says which way is ahead); the point behind the new centre is
+    // the opposite cross point (or the origin after a step of 2).
+    int dir;
+    uint32_t kcost = 0;  // cost of the distant point behind the centre
     {
-        const int o = w <= 4 ? cross_x(w) : cross_y(w);
+        const int o = w == 1 ? -1 : w == 2 ? 1 : w == 3 ? -2 : w == 4 ? 2 : w == 5 ? -1 : 1;
         const bool along_x = (w <= 4) != t;
-        // Switching strategy one: a BMP in the horizontal direction selects
-        // the horizontal diamond, otherwise the vertical one.
         if (along_x) cx += o; else cy += o;
         t = !along_x;
+        dir = o;
+        if (SIMPLIFIED) kcost = w == 1 ? c7[2] : w == 2 ? c7[1] : w <= 4 ? c7[0] : w == 5 ? c7[6] : c7[5];
     }
-    uint32_t ccost = km >> 3;
+    uint32_t cc8 = m & ~7u;  // centre cost << 3
 
-    // Steps 2 and 3: the current diamond around the BMP until the centre wins.
-    uint32_t d0 = 0, d1 = 0;
-    bool v0 = false, v1 = false;
-    int guard = (2 * R + 1) * (2 * R + 1);
-    for (;;) {
-        uint32_t q[4];
-        ev.diamond(cx, cy, t, q);
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            const int ox = t ? ro.dy[r] : ro.dx[r], oy = t ? ro.dx[r] : ro.dy[r];
-            const int x = cx + ox, y = cy + oy;
-            nsp += mark<L>(bm, R, gbase, ro.dv[r] && bd.in(x, y), x, y);
+    // Steps 2 and 3: the current diamond around the BMP until the centre
+    // wins.  New points: F (distant, ahead), N- and N+ (near).
+    uint32_t cF = 0;
+    rc.at(bd, cx, cy);
+    int ca = ev.a00 + __mul24(cy, rs) + cx;  // address of the centre
+    int kc = k00 + __mul24(cy, S) + cx;      // its bitmap index
+    // Bitmap offsets of this lane's point (F for lane 0, N- for lane 1, N+
+    // for lane 2) in the horizontal and vertical diamonds, F ahead on +.
+    const int kh = g == 0 ? 2 : g == 1 ? -S : S;
+    const int kv = g == 0 ? 2 * S : g == 1 ? -1 : 1;
+    const int kmax = S * S;
+    for (int it = 0; it < kmax; ++it) {
+        const bool s = dir > 0;
+        const int ram = rc.am(t), rap = rc.ap(t);
+        const bool vF = (s ? rap : ram) >= 2;
+        const bool vNm = rc.pm(t) != 0, vNp = rc.pp(t) != 0;
+        const int arm2 = t ? 2 * rs : 2, perp = t ? 1 : rs;
+        uint32_t cNm, cNp;
+        ev.pair(ca + (s ? arm2 : -arm2), ca - perp, cF, cNm);
+        cNp = ev.one(ca + perp);
+        {
+            const int ko = t ? kv : kh;
+            mark((g == 0 && vF) || (g == 1 && vNm) || (g == 2 && vNp), kc + ((g == 0 && !s) ? -ko : ko));
         }
-        // Distant points lie on the long arm (x for HDSP), near points on the other.
-        v0 = t ? bd.iny(cy - 2) : bd.inx(cx - 2);
-        v1 = t ? bd.iny(cy + 2) : bd.inx(cx + 2);
-        const bool v2 = t ? bd.inx(cx - 1) : bd.iny(cy - 1);
-        const bool v3 = t ? bd.inx(cx + 1) : bd.iny(cy + 1);
-        d0 = q[0];
-        d1 = q[1];
-        uint32_t m = ccost << 3;
-        m = min(m, key(v0, q[0], 1u));
-        m = min(m, key(v1, q[1], 2u));
-        m = min(m, key(v2, q[2], 3u));
-        m = min(m, key(v3, q[3], 4u));
-        const int ww = (int)(m & 7u);
-        if (ww == 0 || --guard <= 0) break;
-        ccost = m >> 3;
-        if (ww <= 2) {
-            // Distant point: keep the pattern.
-            const int o = ww == 1 ? -2 : 2;
-            if (t) cy += o; else cx += o;
-        } else {
-            // Near point: switching strategy two, to the other diamond.
-            const int o = ww == 3 ? -1 : 1;
-            if (t) cx += o; else cy += o;
-            t = !t;
-        }
+        uint32_t mm = cc8;
+        mm = min(mm, key(vF, cF, 1u));
+        mm = min(mm, key(vNm, cNm, 3u));
+        mm = min(mm, key(vNp, cNp, 4u));
+        const uint32_t ww = mm & 7u;
+        if (ww == 0) break;
+        if (SIMPLIFIED) kcost = ww == 1 ? (cc8 >> 3) : ww == 3 ? cNp : cNm;
+        cc8 = mm & ~7u;
+        // Distant point: keep the pattern.  Near point: switching strategy
+        // two, to the other diamond, moving across the old arm.
+        const bool isF = ww == 1;
+        const int a = isF ? (s ? 2 : -2) : (ww == 4 ? 1 : -1);
+        const bool along_x = isF != t;
+        const int ax = along_x ? a : 0, ay = along_x ? 0 : a;
+        rc.xl += ax;
+        rc.xh -= ax;
+        rc.yl += ay;
+        rc.yh -= ay;
+        ca += __mul24(ay, rs) + ax;
+        kc += __mul24(ay, S) + ax;
+        t = isF ? t : !t;
+        dir = a;
     }
+    cx = rc.xl + bd.lox;
+    cy = rc.yl + bd.loy;
 
     // Step 4: the centre and the two middle points of the current diamond.
-    bool r0 = t ? bd.iny(cy - 1) : bd.inx(cx - 1);
-    bool r1 = t ? bd.iny(cy + 1) : bd.inx(cx + 1);
-    if (simplified) {
+    bool r0 = rc.am(t) >= 1, r1 = rc.ap(t) >= 1;
+    if (SIMPLIFIED) {
         // Simplified DCDS (§IV-C): only the middle point on the side of the
         // smaller distant point; ties -> negative side; with one distant
         // point outside the set, its valid partner's side; with none, both.
+        const bool v0 = rc.am(t) >= 2, v1 = rc.ap(t) >= 2;
+        const uint32_t d0 = dir > 0 ? kcost : cF, d1 = dir > 0 ? cF : kcost;
         bool use0 = true, use1 = true;
         if (v0 && v1) {
             use1 = d1 < d0;
@@ -214,23 +221,22 @@ __device__ SearchOut dcds_search(const Ev& ev, int R, const Bounds& bd, uint32_t
         r0 = r0 && use0;
         r1 = r1 && use1;
     }
-    uint32_t mc[2];
-    ev.mids(cx, cy, t, mc);
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const int ox = t ? 0 : ro.mx[r], oy = t ? ro.mx[r] : 0;
-        const bool act = ro.mv[r] && (ro.mx[r] < 0 ? r0 : r1);
-        nsp += mark<L>(bm, R, gbase, act, cx + ox, cy + oy);
+    const int arm = t ? rs : 1;
+    uint32_t mc0, mc1;
+    ev.pair(ca - arm, ca + arm, mc0, mc1);
+    {
+        const int ka = t ? S : 1;
+        mark((g == 0 && r0) || (g == 1 && r1), g == 0 ? kc - ka : kc + ka);
     }
-    uint32_t m = ccost << 3;
-    m = min(m, key(r0, mc[0], 1u));
-    m = min(m, key(r1, mc[1], 2u));
-    const int wf = (int)(m & 7u);
+    uint32_t mf = cc8;
+    mf = min(mf, key(r0, mc0, 1u));
+    mf = min(mf, key(r1, mc1, 2u));
+    const uint32_t wf = mf & 7u;
     if (wf != 0) {
         const int o = wf == 1 ? -1 : 1;
         if (t) cy += o; else cx += o;
     }
-    return SearchOut{cx, cy, m >> 3, (uint32_t)nsp};
+    return SearchOut{cx, cy, mf >> 3, count()};
 }
 
 }  // namespace me

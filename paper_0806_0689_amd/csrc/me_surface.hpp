@@ -9,43 +9,30 @@ namespace me {
 // ---------------------------------------------------------------------------
 // DCDS over cost surfaces (ideal-condition analysis of §III-C).  16 lanes per
 // surface; the "distortion" of a point is read from the caller's table.
-// Points outside the window are clamped to it for the read (they are masked).
+// Points outside the window read a clamped table entry (their results are masked).
 // ---------------------------------------------------------------------------
 struct SurfaceEval {
     const int32_t* cost;
-    int R;
-    __device__ __forceinline__ uint32_t at(int x, int y) const {
-        x = clampi(x, -R, R);
-        y = clampi(y, -R, R);
-        return (uint32_t)cost[(y + R) * (2 * R + 1) + (x + R)];
+    int S;    // 2R + 1
+    int a00;  // address of (0, 0): R * S + R
+    __device__ __forceinline__ int row() const { return S; }
+    __device__ __forceinline__ uint32_t at(int a) const { return (uint32_t)cost[clampi(a, 0, S * S - 1)]; }
+    __device__ __forceinline__ void pair(int a0, int a1, uint32_t& c0, uint32_t& c1) const {
+        c0 = at(a0);
+        c1 = at(a1);
     }
-    __device__ __forceinline__ void cross(int cx, int cy, bool t, uint32_t (&c)[7]) const {
-        const int ax = t ? 0 : 1, ay = t ? 1 : 0;
-        c[0] = at(cx, cy);
-        c[1] = at(cx - ax, cy - ay);
-        c[2] = at(cx + ax, cy + ay);
-        c[3] = at(cx - 2 * ax, cy - 2 * ay);
-        c[4] = at(cx + 2 * ax, cy + 2 * ay);
-        c[5] = at(cx - ay, cy - ax);
-        c[6] = at(cx + ay, cy + ax);
+    __device__ __forceinline__ uint32_t one(int a0) const { return at(a0); }
+    __device__ __forceinline__ void cross(int a, bool t, uint32_t (&c)[7]) const {
+        const int arm = t ? S : 1, perp = t ? 1 : S;
+        c[0] = at(a);
+        c[1] = at(a - arm);
+        c[2] = at(a + arm);
+        c[3] = at(a - 2 * arm);
+        c[4] = at(a + 2 * arm);
+        c[5] = at(a - perp);
+        c[6] = at(a + perp);
     }
-    __device__ __forceinline__ void cross0(uint32_t (&c)[7]) const { cross(0, 0, false, c); }
-    __device__ __forceinline__ void diamond(int cx, int cy, bool t, uint32_t (&c)[4]) const {
-        const int ax = t ? 0 : 1, ay = t ? 1 : 0;
-        c[0] = at(cx - 2 * ax, cy - 2 * ay);
-        c[1] = at(cx + 2 * ax, cy + 2 * ay);
-        c[2] = at(cx - ay, cy - ax);
-        c[3] = at(cx + ay, cy + ax);
-    }
-    __device__ __forceinline__ void mids(int cx, int cy, bool t, uint32_t (&c)[2]) const {
-        const int ax = t ? 0 : 1, ay = t ? 1 : 0;
-        c[0] = at(cx - ax, cy - ay);
-        c[1] = at(cx + ax, cy + ay);
-    }
-    __device__ __forceinline__ void probe(int sx, int sy, uint32_t (&c)[2]) const {
-        c[0] = at(0, 0);
-        c[1] = at(sx, sy);
-    }
+    __device__ __forceinline__ void cross0(uint32_t (&c)[7]) const { cross(a00, false, c); }
 };
 
 __global__ __launch_bounds__(256) void k_dcds_surface(const int32_t* __restrict__ cost, const uint8_t* __restrict__ valid,
@@ -59,12 +46,10 @@ __global__ __launch_bounds__(256) void k_dcds_surface(const int32_t* __restrict_
     const long long s = (long long)blockIdx.x * (256 / L) + gi;
     uint32_t* bm = smem + gi * BMW;
     for (int i = g; i < BMW; i += L) bm[i] = 0u;
-    Roles<L> ro;
-    ro.init(g);
     __syncthreads();
     if (s >= n) return;
     const int side = 2 * R + 1;
-    SurfaceEval ev{cost + s * side * side, R};
+    SurfaceEval ev{cost + s * side * side, side, R * side + R};
     // The candidate set is the bounding box of the valid mask, plus the origin.
     Bounds bd{-R, R, -R, R};
     if (valid) {
@@ -93,8 +78,8 @@ __global__ __launch_bounds__(256) void k_dcds_surface(const int32_t* __restrict_
         sy = start[2 * s + 1];
         ov = orient != nullptr && orient[s] != 0;
     }
-    const int lane = threadIdx.x & 63;
-    const SearchOut r = dcds_search<L>(ev, R, bd, bm, ro, (lane / L) * L, simplified, seeded, sx, sy, ov);
+    const SearchOut r = simplified ? dcds_search<L, true>(ev, R, bd, bm, g, seeded, sx, sy, ov)
+                                   : dcds_search<L, false>(ev, R, bd, bm, g, seeded, sx, sy, ov);
     if (g == 0) {
         mv[2 * s] = (int16_t)r.x;
         mv[2 * s + 1] = (int16_t)r.y;
