@@ -151,6 +151,44 @@ def learned_leg(me, torch, cur, ref, R, steps, warmup, fs_sad=None, plain=None):
     return res
 
 
+def quality_leg(me, torch, cur, ref, R, steps, warmup):
+    """The measures of §IV for FS, DCDS and DCDS^S on the headline workload
+    (FS vectors as the truth), and the cost of the fused squared-error
+    epilogue and of the per-pair summary kernel."""
+    import numpy as np
+    P, H, W = cur.shape
+    out = {}
+    runs = {}
+    for name, algo in (("fs", me.ME_ALGO_FS), ("dcds", me.ME_ALGO_DCDS), ("dcds_s", me.ME_ALGO_DCDS_S)):
+        runs[name] = me.search(cur, ref, 16, R, algo, sse=True)
+    truth = runs["fs"][0]
+    for name, (mv, sad, nsp, sse) in runs.items():
+        rec = me.frame_quality(mv, sad, sse, truth, block=16)
+        nb = float(rec["blocks"].sum())
+        out[name] = {
+            "mad": float(rec["sad"].sum()) / (nb * 256), "mse": float(rec["sse"].sum()) / (nb * 256),
+            "psnr_db": float(np.mean(rec["psnr"])), "distance": float(rec["dist"].sum()) / nb,
+            "probability": float(rec["equal"].sum()) / nb, "nsp": float(nsp.double().mean()),
+        }
+    fn = lambda: me.search(cur, ref, 16, R, me.ME_ALGO_DCDS, sse=True)  # noqa: E731
+    fn()
+    _, ms_sse, _ = time_launches(fn, steps, warmup, torch)
+    mv, sad, nsp, sse = runs["dcds"]
+    buf = torch.empty(P * me.QUALITY_BYTES, dtype=torch.uint8, device=cur.device)
+    st = torch.cuda.current_stream().cuda_stream
+    qf = lambda: me.me_frame_quality(mv.data_ptr(), sad.data_ptr(), sse.data_ptr(), truth.data_ptr(),  # noqa: E731
+                                     W, H, P, 16, buf.data_ptr(), st)
+    qf()
+    _, ms_q, _ = time_launches(qf, steps, warmup, torch)
+    out["dcds_with_sse_ms"] = ms_sse
+    out["summary_kernel_ms"] = ms_q
+    print("# quality: dcds+sse %.4f ms, summary %.4f ms; psnr fs %.3f dcds %.3f dcds_s %.3f dB; "
+          "dcds distance %.4f probability %.4f" % (
+              ms_sse, ms_q, out["fs"]["psnr_db"], out["dcds"]["psnr_db"], out["dcds_s"]["psnr_db"],
+              out["dcds"]["distance"], out["dcds"]["probability"]), file=sys.stderr, flush=True)
+    return out
+
+
 def config5_leg(me, torch, dev, args):
     """3840x2160, 60 frames, +-31, 16x16: plain DCDS, learned-start DCDS and FS."""
     from synth import make_config
@@ -185,7 +223,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only", default="",
-                    help="comma list of extra legs to run (fs,dcds8,dcds_s,learned,batch,4k); dcds always runs")
+                    help="comma list of extra legs to run (fs,dcds8,dcds_s,learned,batch,quality,4k); "
+                         "dcds always runs")
     ap.add_argument("--sweep", action="store_true",
                     help="time every DCDS kernel configuration (rows per lane x waves per group) and exit")
     ap.add_argument("--calib-copy", action="store_true",
@@ -209,7 +248,8 @@ def main():
     seq = torch.from_numpy(seq_np).to(dev)
     cur, ref = seq[1:], seq[:-1]
     P = FRAMES - 1
-    legs = set(args.only.split(",")) if args.only else {"dcds", "fs", "dcds8", "dcds_s", "learned", "batch", "4k"}
+    legs = set(args.only.split(",")) if args.only else {"dcds", "fs", "dcds8", "dcds_s", "learned", "batch",
+                                                          "quality", "4k"}
     if args.calib_copy:
         src = torch.ones(256 << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -268,6 +308,8 @@ def main():
     if "batch" in legs:
         results["batch"] = batch_leg(me, torch, dev, args)
     extra = {}
+    if "quality" in legs:
+        extra["quality"] = quality_leg(me, torch, cur, ref, RANGE, args.steps, args.warmup)
     if "4k" in legs:
         del seq, cur, ref
         extra["config_4k_r31"] = config5_leg(me, torch, dev, args)

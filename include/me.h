@@ -130,6 +130,46 @@ int me_dcds_ex(const uint8_t *cur, const uint8_t *ref, int32_t width, int32_t he
                me_mv *mv, uint32_t *sad, uint32_t *nsp, void *stream);
 
 /*
+ * Any search with every option: algo ME_ALGO_FS, ME_ALGO_DCDS or
+ * ME_ALGO_DCDS_S; start/orient as me_dcds_ex (DCDS only, else ME_EINVAL).
+ * sse (optional, device, one per block): the sum of squared differences
+ * between the block and the reference block at its vector -- the
+ * motion-compensated block behind the MSE and PSNR of §IV -- computed from
+ * the data already staged for the search (no extra frame reads).
+ * me_fullsearch, me_dcds and me_dcds_ex are this call without sse.
+ */
+int me_search(const uint8_t *cur, const uint8_t *ref, int32_t width, int32_t height, int32_t pitch,
+              int64_t pair_stride, int32_t n_pairs, int32_t block, int32_t range, int32_t algo,
+              const me_mv *start, const uint8_t *orient,
+              me_mv *mv, uint32_t *sad, uint32_t *nsp, uint32_t *sse, void *stream);
+
+/*
+ * Quality of a motion field per frame pair, the measures of §IV (Tables I,
+ * VIII-X): MAD and MSE per pixel and the PSNR of the motion-compensated
+ * frame, and -- given the true vectors (those of full search) -- the mean
+ * distance from them and the probability of finding them.
+ * Inputs are the per-block outputs of one search over n_pairs pairs of
+ * width x height frames (mv, sad, sse from me_search; device) and optional
+ * true vectors mv_true (device, same layout).  out (device, 8-byte aligned)
+ * receives one record per pair.  Distance is Euclidean; a block finds the
+ * true vector when both components are equal.  The sums run in a fixed order.
+ */
+typedef struct {
+    uint64_t sad;     /* sum of the blocks' SAD */
+    uint64_t sse;     /* sum of the blocks' squared error */
+    uint32_t blocks;  /* blocks per pair */
+    uint32_t equal;   /* blocks whose vector equals the true one (0 without mv_true) */
+    double dist;      /* sum of the Euclidean distances to the true vectors (0 without mv_true) */
+    double mad;       /* sad / (blocks * block^2) */
+    double mse;       /* sse / (blocks * block^2) */
+    double psnr;      /* 10 log10(255^2 / mse) in dB; +inf when mse = 0 */
+} me_quality;
+
+int me_frame_quality(const me_mv *mv, const uint32_t *sad, const uint32_t *sse, const me_mv *mv_true,
+                     int32_t width, int32_t height, int32_t n_pairs, int32_t block, me_quality *out,
+                     void *stream);
+
+/*
  * DCDS over caller-given cost surfaces instead of frames: the ideal-condition
  * analysis of §III-C (Table VII) runs the search on a distortion defined for
  * every window point.  cost: device int32 [n][2*range+1][2*range+1] (row = y +
@@ -148,8 +188,8 @@ int me_dcds_surface(const int32_t *cost, const uint8_t *valid, int32_t n, int32_
  * Batched search over many sequences in one persistent launch (this
  * library's addition; the search itself is the one above).  A job is one
  * frame sequence (its own size, pitch and pair count; the block size and the
- * range are the batch's).  Each job's arguments follow me_fullsearch /
- * me_dcds_ex; start/orient must be NULL for ME_ALGO_FS.  Up to 4096 jobs.
+ * range are the batch's).  Each job's arguments follow me_search; start/orient
+ * must be NULL for ME_ALGO_FS.  Up to 4096 jobs.
  *
  * The host copies the job table into a pinned buffer; the device work is
  * {table copy, counter reset, persistent kernel}, captured once per kernel
@@ -167,6 +207,7 @@ typedef struct {
     uint32_t *sad, *nsp;
     const me_mv *start;    /* optional (DCDS only) */
     const uint8_t *orient; /* optional (DCDS only; needs start) */
+    uint32_t *sse;         /* optional: compensated-block squared error, as me_search */
 } me_job;
 
 int me_batch(const me_job *jobs, int32_t n_jobs, int32_t algo, int32_t block, int32_t range, void *stream);

@@ -5,9 +5,10 @@ arguments: every step of a search runs in the library's HIP kernels.  PyTorch
 provides device memory and streams.  There is no CPU fallback: if the library
 is not built, every call raises.
 
-Low-level functions carry the C names (``me_fullsearch``, ``me_dcds``,
-``me_dcds_ex``, ``me_dcds_surface``) and take raw pointers and sizes.  The
-helpers ``fullsearch``, ``dcds`` and ``dcds_surface`` take torch tensors.
+Low-level functions carry the C names (``me_search``, ``me_fullsearch``,
+``me_dcds``, ``me_dcds_ex``, ``me_dcds_surface``, ``me_frame_quality``, ...)
+and take raw pointers and sizes.  The helpers ``search``, ``fullsearch``,
+``dcds``, ``frame_quality`` and ``dcds_surface`` take torch tensors.
 """
 from __future__ import annotations
 
@@ -32,10 +33,12 @@ EXPORTS = [
     "me_status_string",
     "me_set_config",
     "me_get_config",
+    "me_search",
     "me_fullsearch",
     "me_dcds",
     "me_dcds_ex",
     "me_dcds_surface",
+    "me_frame_quality",
     "me_batch",
     "me_autotune",
     "me_autotune_save",
@@ -71,7 +74,14 @@ class MeJob(ctypes.Structure):
         ("pair_stride", ctypes.c_int64),
         ("mv", ctypes.c_void_p), ("sad", ctypes.c_void_p), ("nsp", ctypes.c_void_p),
         ("start", ctypes.c_void_p), ("orient", ctypes.c_void_p),
+        ("sse", ctypes.c_void_p),
     ]
+
+
+# me_quality, one record per frame pair (include/me.h).
+QUALITY_FIELDS = [("sad", "<u8"), ("sse", "<u8"), ("blocks", "<u4"), ("equal", "<u4"), ("dist", "<f8"),
+                  ("mad", "<f8"), ("mse", "<f8"), ("psnr", "<f8")]
+QUALITY_BYTES = 56
 
 
 class MEError(RuntimeError):
@@ -100,6 +110,10 @@ def lib() -> ctypes.CDLL:
         L.me_dcds.restype = ctypes.c_int
         L.me_dcds_ex.argtypes = frame + [i32, vp, vp, vp, vp, vp, vp]
         L.me_dcds_ex.restype = ctypes.c_int
+        L.me_search.argtypes = frame + [i32, vp, vp, vp, vp, vp, vp, vp]
+        L.me_search.restype = ctypes.c_int
+        L.me_frame_quality.argtypes = [vp, vp, vp, vp, i32, i32, i32, i32, vp, vp]
+        L.me_frame_quality.restype = ctypes.c_int
         L.me_dcds_surface.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]
         L.me_dcds_surface.restype = ctypes.c_int
         L.me_set_config.argtypes = [i32, i32, ctypes.POINTER(MeConfig)]
@@ -167,6 +181,16 @@ def me_dcds_ex(cur, ref, width, height, pitch, pair_stride, n_pairs, block, rang
                nsp, stream=0):
     return lib().me_dcds_ex(cur, ref, width, height, pitch, pair_stride, n_pairs, block, range_, algo, start,
                             orient, mv, sad, nsp, stream)
+
+
+def me_search(cur, ref, width, height, pitch, pair_stride, n_pairs, block, range_, algo, start, orient, mv, sad, nsp,
+              sse, stream=0):
+    return lib().me_search(cur, ref, width, height, pitch, pair_stride, n_pairs, block, range_, algo, start, orient,
+                           mv, sad, nsp, sse, stream)
+
+
+def me_frame_quality(mv, sad, sse, mv_true, width, height, n_pairs, block, out, stream=0):
+    return lib().me_frame_quality(mv, sad, sse, mv_true, width, height, n_pairs, block, out, stream)
 
 
 def me_dcds_surface(cost, valid, n, range_, algo, start, orient, mv, cost_out, nsp, stream=0):
@@ -299,9 +323,53 @@ def dcds(cur, ref, block=16, range_=7, algo=ME_ALGO_DCDS, start=None, orient=Non
     return mv, sad, nsp
 
 
-def make_jobs(pairs, block, starts=None, orients=None, outs=None):
+def search(cur, ref, block=16, range_=7, algo=ME_ALGO_DCDS, start=None, orient=None, sse=False, out=None,
+           stream=None):
+    """Any search (algo ME_ALGO_FS, ME_ALGO_DCDS or ME_ALGO_DCDS_S); returns
+    (mv, sad, nsp) and, with sse=True, the per-block squared error of the
+    motion-compensated block as a fourth int32 [P, H/B, W/B] tensor."""
+    torch = _torch()
+    P, H, W, pitch, stride = _frames(cur, ref)
+    mv, sad, nsp = _outputs(P, H // block, W // block, cur.device, out[:3] if out is not None else None)
+    e = None
+    if sse:
+        e = out[3] if out is not None and len(out) > 3 else torch.empty_like(sad)
+    sp = start.data_ptr() if start is not None else None
+    op = orient.data_ptr() if orient is not None else None
+    rc = me_search(cur.data_ptr(), ref.data_ptr(), W, H, pitch, stride, P, block, range_, algo, sp, op,
+                   mv.data_ptr(), sad.data_ptr(), nsp.data_ptr(), e.data_ptr() if e is not None else None,
+                   _stream(stream))
+    _check(rc, "me_search")
+    return (mv, sad, nsp, e) if sse else (mv, sad, nsp)
+
+
+def frame_quality(mv, sad, sse, mv_true=None, block=16, stream=None):
+    """Per-pair quality records (MAD, MSE, PSNR of the compensated frame;
+    distance from and agreement with mv_true) of one search's outputs
+    ([P, H/B, W/B, ...] tensors).  Returns a host numpy structured array with
+    the fields of me_quality (QUALITY_FIELDS)."""
+    import numpy as np
+    torch = _torch()
+    if mv.dim() == 3:
+        mv, sad, sse = mv[None], sad[None], sse[None]
+        mv_true = mv_true[None] if mv_true is not None else None
+    P, hb, wb = mv.shape[:3]
+    for t in (mv, sad, sse) + ((mv_true,) if mv_true is not None else ()):
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("quality inputs must be contiguous GPU tensors")
+    out = torch.empty(max(1, P) * QUALITY_BYTES, dtype=torch.uint8, device=mv.device)
+    rc = me_frame_quality(mv.data_ptr(), sad.data_ptr(), sse.data_ptr(),
+                          mv_true.data_ptr() if mv_true is not None else None, wb * block, hb * block, P, block,
+                          out.data_ptr(), _stream(stream))
+    _check(rc, "me_frame_quality")
+    return out[:P * QUALITY_BYTES].cpu().numpy().view(np.dtype(QUALITY_FIELDS))
+
+
+def make_jobs(pairs, block, starts=None, orients=None, outs=None, sses=None):
     """Job table for me_batch from a list of (cur, ref) tensor pairs ([H, W] or
-    [P, H, W]); allocates outputs unless given.  Returns (ctypes array, outputs)."""
+    [P, H, W]); allocates outputs unless given.  sses: optional per-job int32
+    tensors for the compensated-block squared error.  Returns (ctypes array,
+    outputs)."""
     jobs = (MeJob * max(1, len(pairs)))()
     outputs = []
     for i, (cur, ref) in enumerate(pairs):
@@ -310,16 +378,18 @@ def make_jobs(pairs, block, starts=None, orients=None, outs=None):
         mv, sad, nsp = o
         st = starts[i] if starts is not None else None
         orr = orients[i] if orients is not None else None
+        e = sses[i] if sses is not None else None
         jobs[i] = MeJob(cur.data_ptr(), ref.data_ptr(), W, H, pitch, P, stride, mv.data_ptr(), sad.data_ptr(),
                         nsp.data_ptr(), st.data_ptr() if st is not None else None,
-                        orr.data_ptr() if orr is not None else None)
+                        orr.data_ptr() if orr is not None else None, e.data_ptr() if e is not None else None)
         outputs.append(o)
     return jobs, outputs
 
 
-def batch(pairs, block=16, range_=15, algo=ME_ALGO_DCDS, starts=None, orients=None, outs=None, stream=None):
+def batch(pairs, block=16, range_=15, algo=ME_ALGO_DCDS, starts=None, orients=None, outs=None, sses=None,
+          stream=None):
     """One persistent launch over many sequences; returns one (mv, sad, nsp) per job."""
-    jobs, outputs = make_jobs(pairs, block, starts, orients, outs)
+    jobs, outputs = make_jobs(pairs, block, starts, orients, outs, sses)
     _check(me_batch(jobs, len(pairs), algo, block, range_, _stream(stream)), "me_batch")
     return outputs
 

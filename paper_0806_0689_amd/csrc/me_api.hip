@@ -8,6 +8,7 @@
 #include "me.h"
 #include "me_host.hpp"
 #include "me_kernels.hpp"
+#include "me_quality.hpp"
 #include "me_surface.hpp"
 
 using namespace me;
@@ -90,7 +91,8 @@ namespace {
 template <int B, int RPL, int WPG, int RMAX>
 int launch_dcds_cfg(const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t height, int32_t pitch,
                     int64_t pair_stride, int32_t n_pairs, int32_t range, int flags, const me_mv* start,
-                    const uint8_t* orient, me_mv* mv, uint32_t* sad, uint32_t* nsp, hipStream_t st) {
+                    const uint8_t* orient, me_mv* mv, uint32_t* sad, uint32_t* nsp, uint32_t* sse,
+                    hipStream_t st) {
     using G = DcdsGeo<B, RPL, WPG, RMAX>;
     const size_t lds = dcds_lds_bytes<B, RPL, WPG, RMAX>(range);
     if (lds > kMaxLds) return ME_EUNSUPPORTED;
@@ -108,15 +110,15 @@ int launch_dcds_cfg(const uint8_t* cur, const uint8_t* ref, int32_t width, int32
     const long long grid = (long long)a.tiles_x * a.tiles_y * n_pairs;
     if (grid > INT32_MAX) return ME_EUNSUPPORTED;
     hipLaunchKernelGGL((k_dcds<B, RPL, WPG, RMAX>), dim3((unsigned)grid), dim3(64 * WPG), lds, st, a, flags,
-                       reinterpret_cast<const int16_t*>(start), orient, reinterpret_cast<int16_t*>(mv), sad, nsp);
+                       reinterpret_cast<const int16_t*>(start), orient, reinterpret_cast<int16_t*>(mv), sad, nsp, sse);
     return launched();
 }
 
 template <int B, int RPL, int RMAX>
 int launch_dcds_wpg(int wpg, const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t height, int32_t pitch,
                     int64_t pair_stride, int32_t n_pairs, int32_t range, int flags, const me_mv* start,
-                    const uint8_t* orient, me_mv* mv, uint32_t* sad, uint32_t* nsp, hipStream_t st) {
-#define ME_ARGS cur, ref, width, height, pitch, pair_stride, n_pairs, range, flags, start, orient, mv, sad, nsp, st
+                    const uint8_t* orient, me_mv* mv, uint32_t* sad, uint32_t* nsp, uint32_t* sse, hipStream_t st) {
+#define ME_ARGS cur, ref, width, height, pitch, pair_stride, n_pairs, range, flags, start, orient, mv, sad, nsp, sse, st
     if (wpg == 1) return launch_dcds_cfg<B, RPL, 1, RMAX>(ME_ARGS);
     if (wpg == 2) return launch_dcds_cfg<B, RPL, 2, RMAX>(ME_ARGS);
     return launch_dcds_cfg<B, RPL, 4, RMAX>(ME_ARGS);
@@ -126,7 +128,7 @@ template <int B, int RMAX>
 int launch_dcds_rpl(int rpl, int wpg, const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t height,
                     int32_t pitch, int64_t pair_stride, int32_t n_pairs, int32_t range, int flags,
                     const me_mv* start, const uint8_t* orient, me_mv* mv, uint32_t* sad, uint32_t* nsp,
-                    hipStream_t st) {
+                    uint32_t* sse, hipStream_t st) {
     if (rpl == 1) return launch_dcds_wpg<B, 1, RMAX>(wpg, ME_ARGS);
     if constexpr (B == 16) {
         if (rpl == 4) return launch_dcds_wpg<B, 4, RMAX>(wpg, ME_ARGS);
@@ -136,7 +138,8 @@ int launch_dcds_rpl(int rpl, int wpg, const uint8_t* cur, const uint8_t* ref, in
 
 int launch_dcds(int32_t block, int rpl, int wpg, const uint8_t* cur, const uint8_t* ref, int32_t width,
                 int32_t height, int32_t pitch, int64_t pair_stride, int32_t n_pairs, int32_t range, int flags,
-                const me_mv* start, const uint8_t* orient, me_mv* mv, uint32_t* sad, uint32_t* nsp, hipStream_t st) {
+                const me_mv* start, const uint8_t* orient, me_mv* mv, uint32_t* sad, uint32_t* nsp, uint32_t* sse,
+                hipStream_t st) {
     const int rc = range_class(range);
     if (block == 16) {
         if (rc == 0) return launch_dcds_rpl<16, 7>(rpl, wpg, ME_ARGS);
@@ -186,48 +189,85 @@ ME_EXPORT int me_get_config(int32_t block, int32_t range, me_config* cfg) {
     return ME_OK;
 }
 
+ME_EXPORT int me_search(const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t height, int32_t pitch,
+                        int64_t pair_stride, int32_t n_pairs, int32_t block, int32_t range, int32_t algo,
+                        const me_mv* start, const uint8_t* orient, me_mv* mv, uint32_t* sad, uint32_t* nsp,
+                        uint32_t* sse, void* stream) {
+    int rc = check_frames(cur, ref, width, height, pitch, pair_stride, n_pairs, block, range, mv, sad, nsp);
+    if (rc != ME_OK) return rc;
+    if (algo != ME_ALGO_FS && algo != ME_ALGO_DCDS && algo != ME_ALGO_DCDS_S) return ME_EUNSUPPORTED;
+    if (orient && !start) return ME_EINVAL;
+    if (algo == ME_ALGO_FS && start) return ME_EINVAL;
+    if (n_pairs == 0) return ME_OK;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (algo == ME_ALGO_FS) {
+        const FrameArgs a = frame_args(cur, ref, width, height, pitch, pair_stride, block, range, 1, 1);
+        const long long grid = (long long)a.bw * a.bh * n_pairs;
+        const int nt = fs_threads(range);
+        const bool j4 = fs_rows_per_item(range) == 4;
+        int16_t* mvp = reinterpret_cast<int16_t*>(mv);
+        if (block == 16) {
+            if (j4)
+                hipLaunchKernelGGL((k_fs<16, 4>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<16>(range), st, a, mvp,
+                                   sad, nsp, sse);
+            else
+                hipLaunchKernelGGL((k_fs<16, 1>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<16>(range), st, a, mvp,
+                                   sad, nsp, sse);
+        } else {
+            if (j4)
+                hipLaunchKernelGGL((k_fs<8, 4>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<8>(range), st, a, mvp,
+                                   sad, nsp, sse);
+            else
+                hipLaunchKernelGGL((k_fs<8, 1>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<8>(range), st, a, mvp,
+                                   sad, nsp, sse);
+        }
+        return launched();
+    }
+    const int flags = dcds_flags(algo, cur, ref, width, pitch, pair_stride);
+    int rpl, wpg;
+    current_cfg(block, range_class(range), &rpl, &wpg);
+    return launch_dcds(block, rpl, wpg, cur, ref, width, height, pitch, pair_stride, n_pairs, range, flags, start,
+                       orient, mv, sad, nsp, sse, st);
+}
+
 ME_EXPORT int me_fullsearch(const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t height, int32_t pitch,
                             int64_t pair_stride, int32_t n_pairs, int32_t block, int32_t range, me_mv* mv,
                             uint32_t* sad, uint32_t* nsp, void* stream) {
-    int rc = check_frames(cur, ref, width, height, pitch, pair_stride, n_pairs, block, range, mv, sad, nsp);
-    if (rc != ME_OK || n_pairs == 0) return rc;
-    const FrameArgs a = frame_args(cur, ref, width, height, pitch, pair_stride, block, range, 1, 1);
-    const long long grid = (long long)a.bw * a.bh * n_pairs;
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const int nt = fs_threads(range);
-    const bool j4 = fs_rows_per_item(range) == 4;
-    int16_t* mvp = reinterpret_cast<int16_t*>(mv);
-    if (block == 16) {
-        if (j4) hipLaunchKernelGGL((k_fs<16, 4>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<16>(range), st, a, mvp, sad, nsp);
-        else hipLaunchKernelGGL((k_fs<16, 1>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<16>(range), st, a, mvp, sad, nsp);
-    } else {
-        if (j4) hipLaunchKernelGGL((k_fs<8, 4>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<8>(range), st, a, mvp, sad, nsp);
-        else hipLaunchKernelGGL((k_fs<8, 1>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<8>(range), st, a, mvp, sad, nsp);
-    }
-    return launched();
+    return me_search(cur, ref, width, height, pitch, pair_stride, n_pairs, block, range, ME_ALGO_FS, nullptr,
+                     nullptr, mv, sad, nsp, nullptr, stream);
 }
 
 ME_EXPORT int me_dcds_ex(const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t height, int32_t pitch,
                          int64_t pair_stride, int32_t n_pairs, int32_t block, int32_t range, int32_t algo,
                          const me_mv* start, const uint8_t* orient, me_mv* mv, uint32_t* sad, uint32_t* nsp,
                          void* stream) {
-    int rc = check_frames(cur, ref, width, height, pitch, pair_stride, n_pairs, block, range, mv, sad, nsp);
-    if (rc != ME_OK) return rc;
     if (algo != ME_ALGO_DCDS && algo != ME_ALGO_DCDS_S) return ME_EUNSUPPORTED;
-    if (orient && !start) return ME_EINVAL;
-    if (n_pairs == 0) return ME_OK;
-    const int flags = dcds_flags(algo, cur, ref, width, pitch, pair_stride);
-    int rpl, wpg;
-    current_cfg(block, range_class(range), &rpl, &wpg);
-    return launch_dcds(block, rpl, wpg, cur, ref, width, height, pitch, pair_stride, n_pairs, range, flags, start,
-                       orient, mv, sad, nsp, reinterpret_cast<hipStream_t>(stream));
+    return me_search(cur, ref, width, height, pitch, pair_stride, n_pairs, block, range, algo, start, orient, mv,
+                     sad, nsp, nullptr, stream);
 }
 
 ME_EXPORT int me_dcds(const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t height, int32_t pitch,
                       int64_t pair_stride, int32_t n_pairs, int32_t block, int32_t range, me_mv* mv, uint32_t* sad,
                       uint32_t* nsp, void* stream) {
-    return me_dcds_ex(cur, ref, width, height, pitch, pair_stride, n_pairs, block, range, ME_ALGO_DCDS, nullptr,
-                      nullptr, mv, sad, nsp, stream);
+    return me_search(cur, ref, width, height, pitch, pair_stride, n_pairs, block, range, ME_ALGO_DCDS, nullptr,
+                     nullptr, mv, sad, nsp, nullptr, stream);
+}
+
+ME_EXPORT int me_frame_quality(const me_mv* mv, const uint32_t* sad, const uint32_t* sse, const me_mv* mv_true,
+                               int32_t width, int32_t height, int32_t n_pairs, int32_t block, me_quality* out,
+                               void* stream) {
+    if (width <= 0 || height <= 0 || n_pairs < 0) return ME_EINVAL;
+    if (block != 8 && block != 16) return ME_EUNSUPPORTED;
+    if (width % block || height % block) return ME_EINVAL;
+    if (n_pairs == 0) return ME_OK;
+    if (!mv || !sad || !sse || !out) return ME_EINVAL;
+    if (!aligned(out, 8)) return ME_EINVAL;
+    const long long nb = (long long)(width / block) * (height / block);
+    if (nb * n_pairs > (long long)INT32_MAX) return ME_EUNSUPPORTED;
+    hipLaunchKernelGGL(k_frame_quality, dim3((unsigned)n_pairs), dim3(256), 0, reinterpret_cast<hipStream_t>(stream),
+                       reinterpret_cast<const int16_t*>(mv), sad, sse, reinterpret_cast<const int16_t*>(mv_true),
+                       (int)nb, block, reinterpret_cast<QualityOut*>(out));
+    return launched();
 }
 
 ME_EXPORT int me_dcds_surface(const int32_t* cost, const uint8_t* valid, int32_t n, int32_t range, int32_t algo,

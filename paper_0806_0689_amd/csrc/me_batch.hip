@@ -190,6 +190,7 @@ int batch_launch(const me_job* jobs, int32_t n_jobs, int32_t algo, int32_t block
         b.mv = reinterpret_cast<int16_t*>(j.mv);
         b.sad = j.sad;
         b.nsp = j.nsp;
+        b.sse = j.sse;
         total += (long long)b.a.tiles_x * b.a.tiles_y * j.n_pairs;
         if (total > INT32_MAX) return ME_EUNSUPPORTED;
         tab.push_back(b);

@@ -17,6 +17,7 @@ struct BatchJob {
     int16_t* mv;
     uint32_t* sad;
     uint32_t* nsp;
+    uint32_t* sse;           // optional compensated-block squared error
 };
 
 struct BatchTable {
@@ -80,7 +81,7 @@ __global__ __launch_bounds__(64 * WPG) void k_dcds_batch(const BatchTable* __res
             const int pair = r / jb.a.tiles_y;
             if (t != t0) __syncthreads();  // the previous tile's waves are done with LDS
             dcds_tile<B, RPL, WPG, RMAX>(smem, jb.a, jb.flags, pair, tx, ty, jb.start, jb.orient, jb.mv, jb.sad,
-                                         jb.nsp);
+                                         jb.nsp, jb.sse);
         }
     }
 }
@@ -105,7 +106,7 @@ __global__ __launch_bounds__(256) void k_fs_batch(const BatchTable* __restrict__
             const int by = r % jb.a.bh;
             const int pair = r / jb.a.bh;
             if (t != t0) __syncthreads();
-            fs_block<B, J>(smem, jb.a, pair, bx, by, jb.mv, jb.sad, jb.nsp, blockDim.x);
+            fs_block<B, J>(smem, jb.a, pair, bx, by, jb.mv, jb.sad, jb.nsp, jb.sse, blockDim.x);
         }
     }
 }

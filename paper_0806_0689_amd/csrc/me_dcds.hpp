@@ -137,6 +137,30 @@ struct FrameEval {
 
     __device__ __forceinline__ uint32_t one(int a0) const { return group_sum<L>(pt<false>(a0, 0u)); }
 
+    // Sum of squared differences between the block and the reference block at
+    // address a (the motion-compensated block), over the whole group:
+    // sum (f - c)^2 = sum f^2 + sum c^2 - 2 sum f c, each term one
+    // v_dot4_u32_u8 per word; the u32 arithmetic is exact modulo 2^32 and the
+    // result is below 2^24.
+    __device__ __forceinline__ uint32_t sse(int a) const {
+        const lds_words w = lds_at((uint32_t)a & ~3u);
+        uint32_t ff = 0, fc = 0, cc = 0;
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+            uint32_t d[K + 1];
+#pragma unroll
+            for (int k = 0; k <= K; ++k) d[k] = w[j * JW + k];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const uint32_t f = __builtin_amdgcn_alignbyte(d[k + 1], d[k], (uint32_t)a);
+                ff = __builtin_amdgcn_udot4(f, f, ff, false);
+                fc = __builtin_amdgcn_udot4(f, cur[j][k], fc, false);
+                cc = __builtin_amdgcn_udot4(cur[j][k], cur[j][k], cc, false);
+            }
+        }
+        return group_sum<L>(ff + cc - 2u * fc);
+    }
+
     // HCSP at the origin: the centre row is read once (K + 2 words from 4
     // bytes left of the block), shifted by 2 bytes, and v_qsad_pk_u16_u8
     // yields the offsets -2, -1, 0, +1 together; the rows above and below are
@@ -208,7 +232,7 @@ template <int B, int RPL, int WPG, int RMAX>
 __device__ __forceinline__ void dcds_tile(uint32_t* smem, const FrameArgs& a, int flags, int pair, int tx, int ty,
                                           const int16_t* __restrict__ start, const uint8_t* __restrict__ orient,
                                           int16_t* __restrict__ mv, uint32_t* __restrict__ sad,
-                                          uint32_t* __restrict__ nsp) {
+                                          uint32_t* __restrict__ nsp, uint32_t* __restrict__ sse) {
     using G = DcdsGeo<B, RPL, WPG, RMAX>;
     constexpr int L = G::L, K = G::K;
     const int R = a.R;
@@ -270,11 +294,14 @@ __device__ __forceinline__ void dcds_tile(uint32_t* smem, const FrameArgs& a, in
         const SearchOut r = (flags & DCDS_SIMPLIFIED) != 0
                                 ? dcds_search<L, true>(ev, R, bd, bm, g, seeded, sx, sy, ov)
                                 : dcds_search<L, false>(ev, R, bd, bm, g, seeded, sx, sy, ov);
+        // Optional epilogue: the squared error of the compensated block.
+        const uint32_t e = sse ? ev.sse(ev.a00 + __mul24(r.y, G::WDW * 4) + r.x) : 0u;
         if (g == 0) {
             mv[2 * idx] = (int16_t)r.x;
             mv[2 * idx + 1] = (int16_t)r.y;
             sad[idx] = r.cost;
             nsp[idx] = r.nsp;
+            if (sse) sse[idx] = e;
         }
     }
 }
@@ -282,14 +309,15 @@ __device__ __forceinline__ void dcds_tile(uint32_t* smem, const FrameArgs& a, in
 template <int B, int RPL, int WPG, int RMAX>
 __global__ __launch_bounds__(64 * WPG) void k_dcds(FrameArgs a, int flags, const int16_t* __restrict__ start,
                                                     const uint8_t* __restrict__ orient, int16_t* __restrict__ mv,
-                                                    uint32_t* __restrict__ sad, uint32_t* __restrict__ nsp) {
+                                                    uint32_t* __restrict__ sad, uint32_t* __restrict__ nsp,
+                                                    uint32_t* __restrict__ sse) {
     extern __shared__ uint32_t smem[];
     int t = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = t % a.tiles_x;
     t /= a.tiles_x;
     const int ty = t % a.tiles_y;
     const int pair = t / a.tiles_y;
-    dcds_tile<B, RPL, WPG, RMAX>(smem, a, flags, pair, tx, ty, start, orient, mv, sad, nsp);
+    dcds_tile<B, RPL, WPG, RMAX>(smem, a, flags, pair, tx, ty, start, orient, mv, sad, nsp, sse);
 }
 
 }  // namespace me

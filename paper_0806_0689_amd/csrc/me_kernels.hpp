@@ -110,7 +110,7 @@ __device__ __forceinline__ uint32_t fs_items_min(const uint32_t* win, int WD, in
 template <int B, int J>
 __device__ __forceinline__ void fs_block(uint32_t* smem, const FrameArgs& a, int pair, int bx, int by,
                                          int16_t* __restrict__ mv, uint32_t* __restrict__ sad,
-                                         uint32_t* __restrict__ nsp, int nt) {
+                                         uint32_t* __restrict__ nsp, uint32_t* __restrict__ sse, int nt) {
     const int R = a.R;
     const int MW = margin_words(R);
     const int G = fs_groups(R);
@@ -133,36 +133,56 @@ __device__ __forceinline__ void fs_block(uint32_t* smem, const FrameArgs& a, int
     const int loy = max(-R, -y0), hiy = min(R, a.H - B - y0);
     const int items = G * DG;
     uint32_t best = fs_items_min<B, J>(win, WD, G, items, R, MW, cur, a.pitch / 4, lox, hix, loy, hiy, nt);
-    // Workgroup minimum.
+    // Workgroup minimum: every thread reads the per-wave minima.
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) best = min(best, (uint32_t)__shfl_xor((int)best, o, 64));
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = best;
     __syncthreads();
+    uint32_t k = part[0];
+    for (int w = 1; w < nt / 64; ++w) k = min(k, part[w]);
+    const int sgn = (int)(k & 1u);
+    const int y = (int)((k >> 1) & 63u) - 31;
+    const int l1 = (int)((k >> 7) & 63u);
+    const int ax = l1 - abs(y);
+    const int x = sgn ? ax : -ax;
+    const long long idx = ((long long)pair * a.bh + by) * a.bw + bx;
     if (threadIdx.x == 0) {
-        uint32_t k = part[0];
-        for (int w = 1; w < nt / 64; ++w) k = min(k, part[w]);
-        const int sgn = (int)(k & 1u);
-        const int y = (int)((k >> 1) & 63u) - 31;
-        const int l1 = (int)((k >> 7) & 63u);
-        const int ax = l1 - abs(y);
-        const long long idx = ((long long)pair * a.bh + by) * a.bw + bx;
-        mv[2 * idx] = (int16_t)(sgn ? ax : -ax);
+        mv[2 * idx] = (int16_t)x;
         mv[2 * idx + 1] = (int16_t)y;
         sad[idx] = k >> 13;
         nsp[idx] = (uint32_t)((hix - lox + 1) * (hiy - loy + 1));
+    }
+    // Optional epilogue: squared error of the compensated block, one word of
+    // the block per lane of the first wave (sum (f - c)^2 = f.f + c.c - 2 f.c
+    // with v_dot4_u32_u8, exact modulo 2^32).
+    if (sse && threadIdx.x < 64) {
+        constexpr int K = B / 4;
+        uint32_t e = 0;
+        if (threadIdx.x < B * K) {
+            const int v = threadIdx.x / K, kw = threadIdx.x % K;
+            const int b = x + 4 * MW + 4 * kw;  // byte column in the window row
+            const uint32_t* row = win + (y + R + v) * WD + (b >> 2);
+            const uint32_t f = __builtin_amdgcn_alignbyte(row[1], row[0], (uint32_t)b);
+            const uint32_t c = cur[v * (a.pitch / 4) + kw];
+            e = __builtin_amdgcn_udot4(f, f, 0u, false) + __builtin_amdgcn_udot4(c, c, 0u, false) -
+                2u * __builtin_amdgcn_udot4(f, c, 0u, false);
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) e += (uint32_t)__shfl_xor((int)e, o, 64);
+        if (threadIdx.x == 0) sse[idx] = e;
     }
 }
 
 template <int B, int J>
 __global__ __launch_bounds__(256) void k_fs(FrameArgs a, int16_t* __restrict__ mv, uint32_t* __restrict__ sad,
-                                            uint32_t* __restrict__ nsp) {
+                                            uint32_t* __restrict__ nsp, uint32_t* __restrict__ sse) {
     extern __shared__ uint32_t smem[];
     int t = blockIdx.x;
     const int bx = t % a.bw;
     t /= a.bw;
     const int by = t % a.bh;
     const int pair = t / a.bh;
-    fs_block<B, J>(smem, a, pair, bx, by, mv, sad, nsp, blockDim.x);
+    fs_block<B, J>(smem, a, pair, bx, by, mv, sad, nsp, sse, blockDim.x);
 }
 
 }  // namespace me

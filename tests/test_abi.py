@@ -48,7 +48,15 @@ def _frame_call(fn, **kw):
               a["range_"], a["mv"], a["sad"], a["nsp"], 0)
 
 
-@pytest.mark.parametrize("fn", [me.me_fullsearch, me.me_dcds])
+def _search_fs(*a):
+    return me.me_search(*a[:9], me.ME_ALGO_FS, None, None, *a[9:12], None, a[12])
+
+
+def _search_dcds_sse(*a):
+    return me.me_search(*a[:9], me.ME_ALGO_DCDS_S, None, None, *a[9:12], P, a[12])
+
+
+@pytest.mark.parametrize("fn", [me.me_fullsearch, me.me_dcds, _search_fs, _search_dcds_sse])
 @pytest.mark.parametrize("kw,status", [
     (dict(cur=None), me.ME_EINVAL),
     (dict(ref=None), me.ME_EINVAL),
@@ -83,6 +91,27 @@ def test_dcds_ex_checks():
     assert me.me_dcds_ex(*base, me.ME_ALGO_FS, None, None, P, P, P, 0) == me.ME_EUNSUPPORTED
     assert me.me_dcds_ex(*base, me.ME_ALGO_DCDS, None, P, P, P, P, 0) == me.ME_EINVAL  # orient without start
     assert me.me_dcds_ex(P, P, 64, 32, 64, 2048, 0, 16, 7, me.ME_ALGO_DCDS_S, P, P, P, P, P, 0) == me.ME_OK
+
+
+def test_search_checks():
+    base = (P, P, 64, 32, 64, 2048, 1, 16, 7)
+    assert me.me_search(*base, 7, None, None, P, P, P, None, 0) == me.ME_EUNSUPPORTED  # unknown algo
+    assert me.me_search(*base, me.ME_ALGO_FS, P, None, P, P, P, None, 0) == me.ME_EINVAL  # FS has no start
+    assert me.me_search(*base, me.ME_ALGO_DCDS, None, P, P, P, P, P, 0) == me.ME_EINVAL  # orient without start
+    assert me.me_search(P, P, 64, 32, 64, 2048, 0, 16, 7, me.ME_ALGO_FS, None, None, P, P, P, P, 0) == me.ME_OK
+
+
+def test_frame_quality_checks():
+    q = me.me_frame_quality
+    assert q(P, P, P, None, 64, 32, 1, 16, P + 4, 0) == me.ME_EINVAL      # misaligned record array
+    assert q(None, P, P, None, 64, 32, 1, 16, P, 0) == me.ME_EINVAL
+    assert q(P, P, None, None, 64, 32, 1, 16, P, 0) == me.ME_EINVAL
+    assert q(P, P, P, None, 64, 32, 1, 16, None, 0) == me.ME_EINVAL
+    assert q(P, P, P, None, 0, 32, 1, 16, P, 0) == me.ME_EINVAL
+    assert q(P, P, P, None, 72, 32, 1, 16, P, 0) == me.ME_EINVAL          # not a multiple of the block
+    assert q(P, P, P, None, 64, 32, -1, 16, P, 0) == me.ME_EINVAL
+    assert q(P, P, P, None, 64, 32, 1, 12, P, 0) == me.ME_EUNSUPPORTED
+    assert q(None, None, None, None, 64, 32, 0, 16, None, 0) == me.ME_OK  # nothing to do
 
 
 def test_surface_checks():
