@@ -189,6 +189,40 @@ def quality_leg(me, torch, cur, ref, R, steps, warmup):
     return out
 
 
+def mvp_leg(me, torch, cur, ref, steps, warmup):
+    """The MVP statistics of §II-C over the headline sequence in the paper's
+    +-7 window: time of one full pass (full search with the statistics
+    epilogue over all pairs, then the tables), and the synthetic data's
+    distribution beside the paper's Table III / Fig. 3 figures."""
+    R = 7
+    n = 2 * R + 1
+    counts = (torch.zeros(n * n, dtype=torch.int32, device=cur.device),
+              torch.zeros((9, n * n), dtype=torch.int32, device=cur.device),
+              torch.zeros((n * n, 25), dtype=torch.int32, device=cur.device))
+
+    def one():
+        for c in counts:
+            c.zero_()
+        me.mvp_stats(cur, ref, 16, R, counts=counts)
+
+    one()
+    _, ms, _ = time_launches(one, max(3, min(steps, 10)), warmup, torch)
+    t = me.mvp_tables(counts, R)
+    out = {
+        "ms_per_pass": ms,
+        "p00": float(t["quarter"][0, 0]),
+        "bx": [float(v) for v in t["bx"][R - 2:R + 3]], "by": [float(v) for v in t["by"][R - 2:R + 3]],
+        "ax_var": float(sum(t["ax"][i] * (i - R) ** 2 for i in range(n))),
+        "ay_var": float(sum(t["ay"][i] * (i - R) ** 2 for i in range(n))),
+        "regions": [float(v) for v in t["regions"]], "eta": [float(v) for v in t["eta"]],
+        "paper": {"p00": 0.5805, "bx": [0.0151, 0.0718, 0.5805, 0.0562, 0.0440],
+                  "by": [0.0031, 0.0295, 0.5805, 0.0277, 0.0035]},
+    }
+    print("# mvp: %.4f ms per pass; P(0,0) %.4f; var x %.3f y %.3f; eta %s" % (
+        ms, out["p00"], out["ax_var"], out["ay_var"], [round(v, 4) for v in out["eta"]]), file=sys.stderr, flush=True)
+    return out
+
+
 def config5_leg(me, torch, dev, args):
     """3840x2160, 60 frames, +-31, 16x16: plain DCDS, learned-start DCDS and FS."""
     from synth import make_config
@@ -223,7 +257,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only", default="",
-                    help="comma list of extra legs to run (fs,dcds8,dcds_s,learned,batch,quality,4k); "
+                    help="comma list of extra legs to run (fs,dcds8,dcds_s,learned,batch,quality,mvp,4k); "
                          "dcds always runs")
     ap.add_argument("--sweep", action="store_true",
                     help="time every DCDS kernel configuration (rows per lane x waves per group) and exit")
@@ -249,7 +283,7 @@ def main():
     cur, ref = seq[1:], seq[:-1]
     P = FRAMES - 1
     legs = set(args.only.split(",")) if args.only else {"dcds", "fs", "dcds8", "dcds_s", "learned", "batch",
-                                                          "quality", "4k"}
+                                                          "quality", "mvp", "4k"}
     if args.calib_copy:
         src = torch.ones(256 << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -310,6 +344,8 @@ def main():
     extra = {}
     if "quality" in legs:
         extra["quality"] = quality_leg(me, torch, cur, ref, RANGE, args.steps, args.warmup)
+    if "mvp" in legs:
+        extra["mvp_stats_r7"] = mvp_leg(me, torch, cur, ref, args.steps, args.warmup)
     if "4k" in legs:
         del seq, cur, ref
         extra["config_4k_r31"] = config5_leg(me, torch, dev, args)

@@ -170,6 +170,48 @@ int me_frame_quality(const me_mv *mv, const uint32_t *sad, const uint32_t *sse, 
                      void *stream);
 
 /*
+ * Statistics of the motion-vector probability (MVP) distribution of §II-C,
+ * from full search over n_pairs frame pairs (frames as me_fullsearch).  With
+ * n = 2 range + 1 and vector index (y + range) n + (x + range), the call adds
+ * every block to three device counter arrays (uint32; the caller zeroes
+ * them, so several sequences can be accumulated as the paper does):
+ *   hist[n*n]      the full-search vector (Tables II and III, Fig. 3);
+ *   d1[9][n*n]     the vector given P, the best point of the CDS first-step
+ *                  cross {(x, 0): |x| <= 2} U {(0, y): |y| <= 2} -- the prior
+ *                  distribution of Eq. (4); P index x + 2 for (x, 0), then
+ *                  5, 6, 7, 8 for (0, -2), (0, -1), (0, 1), (0, 2);
+ *   d2[n*n][25]    the best point of the central 5x5 square given the vector
+ *                  -- the posterior distribution of Eq. (6); point index
+ *                  (y + 2) 5 + (x + 2).
+ * "Best" uses full search's order (SAD, then |x| + |y|, then y, then x) over
+ * the points inside the block's candidate set.  +y points down the frame.
+ */
+int me_mvp_stats(const uint8_t *cur, const uint8_t *ref, int32_t width, int32_t height, int32_t pitch,
+                 int64_t pair_stride, int32_t n_pairs, int32_t block, int32_t range,
+                 uint32_t *hist, uint32_t *d1, uint32_t *d2, void *stream);
+
+/*
+ * The tables of §II-C from those counters, as me_mvp_tables_size(range)
+ * doubles at out (device, 8-byte aligned), in this order (N = total count):
+ *   quarter[(range+1)^2]  Table II: count at (+-x, +-y) / N, row |y|, column |x|
+ *   Ax[n], Ay[n]          Table III: marginal of x (of y) / N, index d + range
+ *   Bx[n], By[n]          Table III: vectors (d, 0) (and (0, d)) / N
+ *   regions[5]            Fig. 3: 5x5 square, 5x5 diamond, 5x5 cross, 3x3
+ *                         square, 5x3 flat diamond
+ *   eta[5]                Table VI / Eq. (7): P_1 / n_1 of the 3x3 square
+ *                         (BBGDS), large diamond (DS), 5x5 cross (CDS),
+ *                         hexagon (HEXBS) and HCSP (DCDS)
+ *   d1[9][n*n]            Eq. (4), each row normalised to 1 (0 if empty)
+ *   d2[n*n][25]           Eq. (6), each row normalised to 1 (0 if empty)
+ *   t1[25], t2[25]        d2 given a vector in T1 = [4,7] x [4,7] and
+ *                         T2 = [-7,-4] x [4,7], normalised to 1
+ * me_mvp_tables_size returns ME_EUNSUPPORTED for a range outside 1..31.
+ */
+int32_t me_mvp_tables_size(int32_t range);
+int me_mvp_tables(const uint32_t *hist, const uint32_t *d1, const uint32_t *d2, int32_t range, double *out,
+                  void *stream);
+
+/*
  * DCDS over caller-given cost surfaces instead of frames: the ideal-condition
  * analysis of §III-C (Table VII) runs the search on a distortion defined for
  * every window point.  cost: device int32 [n][2*range+1][2*range+1] (row = y +

@@ -7,7 +7,8 @@ TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 The arithmetic lives in ``me_oracle.c`` (plain scalar C, single-threaded); this
 module only builds it with gcc and marshals numpy arrays through ctypes.
 ``cnn.py`` holds the fp64 numpy oracle of the learned start proposer and
-``quality.py`` that of the quality measures (MAD, MSE, PSNR, distance).
+``quality.py`` that of the quality measures (MAD, MSE, PSNR, distance) and
+``mvp.py`` that of the MVP statistics of §II-C.
 """
 from __future__ import annotations
 

@@ -39,6 +39,9 @@ EXPORTS = [
     "me_dcds_ex",
     "me_dcds_surface",
     "me_frame_quality",
+    "me_mvp_stats",
+    "me_mvp_tables_size",
+    "me_mvp_tables",
     "me_batch",
     "me_autotune",
     "me_autotune_save",
@@ -114,6 +117,12 @@ def lib() -> ctypes.CDLL:
         L.me_search.restype = ctypes.c_int
         L.me_frame_quality.argtypes = [vp, vp, vp, vp, i32, i32, i32, i32, vp, vp]
         L.me_frame_quality.restype = ctypes.c_int
+        L.me_mvp_stats.argtypes = frame + [vp, vp, vp, vp]
+        L.me_mvp_stats.restype = ctypes.c_int
+        L.me_mvp_tables_size.argtypes = [i32]
+        L.me_mvp_tables_size.restype = i32
+        L.me_mvp_tables.argtypes = [vp, vp, vp, i32, vp, vp]
+        L.me_mvp_tables.restype = ctypes.c_int
         L.me_dcds_surface.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]
         L.me_dcds_surface.restype = ctypes.c_int
         L.me_set_config.argtypes = [i32, i32, ctypes.POINTER(MeConfig)]
@@ -191,6 +200,19 @@ def me_search(cur, ref, width, height, pitch, pair_stride, n_pairs, block, range
 
 def me_frame_quality(mv, sad, sse, mv_true, width, height, n_pairs, block, out, stream=0):
     return lib().me_frame_quality(mv, sad, sse, mv_true, width, height, n_pairs, block, out, stream)
+
+
+def me_mvp_stats(cur, ref, width, height, pitch, pair_stride, n_pairs, block, range_, hist, d1, d2, stream=0):
+    return lib().me_mvp_stats(cur, ref, width, height, pitch, pair_stride, n_pairs, block, range_, hist, d1, d2,
+                              stream)
+
+
+def me_mvp_tables_size(range_):
+    return lib().me_mvp_tables_size(range_)
+
+
+def me_mvp_tables(hist, d1, d2, range_, out, stream=0):
+    return lib().me_mvp_tables(hist, d1, d2, range_, out, stream)
 
 
 def me_dcds_surface(cost, valid, n, range_, algo, start, orient, mv, cost_out, nsp, stream=0):
@@ -363,6 +385,51 @@ def frame_quality(mv, sad, sse, mv_true=None, block=16, stream=None):
                           out.data_ptr(), _stream(stream))
     _check(rc, "me_frame_quality")
     return out[:P * QUALITY_BYTES].cpu().numpy().view(np.dtype(QUALITY_FIELDS))
+
+
+def mvp_stats(cur, ref, block=16, range_=7, counts=None, stream=None):
+    """Adds the blocks of these pairs to the MVP counters (hist [n*n], d1
+    [9, n*n], d2 [n*n, 25] int32 tensors, n = 2 range + 1; zeroed here unless
+    given) and returns them."""
+    torch = _torch()
+    P, H, W, pitch, stride = _frames(cur, ref)
+    n = 2 * range_ + 1
+    if counts is None:
+        counts = (torch.zeros(n * n, dtype=torch.int32, device=cur.device),
+                  torch.zeros((9, n * n), dtype=torch.int32, device=cur.device),
+                  torch.zeros((n * n, 25), dtype=torch.int32, device=cur.device))
+    hist, d1, d2 = counts
+    rc = me_mvp_stats(cur.data_ptr(), ref.data_ptr(), W, H, pitch, stride, P, block, range_, hist.data_ptr(),
+                      d1.data_ptr(), d2.data_ptr(), _stream(stream))
+    _check(rc, "me_mvp_stats")
+    return counts
+
+
+def mvp_tables(counts, range_, stream=None):
+    """The tables of §II-C from mvp_stats counters, as host numpy arrays:
+    quarter [R+1, R+1], ax, ay, bx, by [2R+1], regions [5], eta [5],
+    d1 [9, 2R+1, 2R+1], d2 [2R+1, 2R+1, 5, 5], t1, t2 [5, 5]."""
+    torch = _torch()
+    hist, d1, d2 = counts
+    size = me_mvp_tables_size(range_)
+    if size < 0:
+        raise MEError(size, "me_mvp_tables_size")
+    out = torch.empty(size, dtype=torch.float64, device=hist.device)
+    _check(me_mvp_tables(hist.data_ptr(), d1.data_ptr(), d2.data_ptr(), range_, out.data_ptr(), _stream(stream)),
+           "me_mvp_tables")
+    v = out.cpu().numpy()
+    R, n = range_, 2 * range_ + 1
+    parts, at = {}, 0
+    for name, shape in (("quarter", (R + 1, R + 1)), ("ax", (n,)), ("ay", (n,)), ("bx", (n,)), ("by", (n,)),
+                        ("regions", (5,)), ("eta", (5,)), ("d1", (9, n, n)), ("d2", (n, n, 5, 5)),
+                        ("t1", (5, 5)), ("t2", (5, 5))):
+        k = 1
+        for s_ in shape:
+            k *= s_
+        parts[name] = v[at:at + k].reshape(shape)
+        at += k
+    assert at == size
+    return parts
 
 
 def make_jobs(pairs, block, starts=None, orients=None, outs=None, sses=None):

@@ -8,6 +8,7 @@
 #include "me.h"
 #include "me_host.hpp"
 #include "me_kernels.hpp"
+#include "me_mvp.hpp"
 #include "me_quality.hpp"
 #include "me_surface.hpp"
 
@@ -267,6 +268,43 @@ ME_EXPORT int me_frame_quality(const me_mv* mv, const uint32_t* sad, const uint3
     hipLaunchKernelGGL(k_frame_quality, dim3((unsigned)n_pairs), dim3(256), 0, reinterpret_cast<hipStream_t>(stream),
                        reinterpret_cast<const int16_t*>(mv), sad, sse, reinterpret_cast<const int16_t*>(mv_true),
                        (int)nb, block, reinterpret_cast<QualityOut*>(out));
+    return launched();
+}
+
+ME_EXPORT int me_mvp_stats(const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t height, int32_t pitch,
+                           int64_t pair_stride, int32_t n_pairs, int32_t block, int32_t range, uint32_t* hist,
+                           uint32_t* d1, uint32_t* d2, void* stream) {
+    int rc = check_frames(cur, ref, width, height, pitch, pair_stride, n_pairs, block, range, hist, d1, d2);
+    if (rc != ME_OK || n_pairs == 0) return rc;
+    if (!aligned(hist, 4) || !aligned(d1, 4) || !aligned(d2, 4)) return ME_EINVAL;
+    const FrameArgs a = frame_args(cur, ref, width, height, pitch, pair_stride, block, range, 1, 1);
+    const long long grid = (long long)a.bw * a.bh * n_pairs;
+    const int nt = fs_threads(range);
+    const bool j4 = fs_rows_per_item(range) == 4;
+    const MvpCounts mc{hist, d1, d2};
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (block == 16) {
+        if (j4) hipLaunchKernelGGL((k_fs_stats<16, 4>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<16>(range), st, a, mc);
+        else hipLaunchKernelGGL((k_fs_stats<16, 1>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<16>(range), st, a, mc);
+    } else {
+        if (j4) hipLaunchKernelGGL((k_fs_stats<8, 4>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<8>(range), st, a, mc);
+        else hipLaunchKernelGGL((k_fs_stats<8, 1>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<8>(range), st, a, mc);
+    }
+    return launched();
+}
+
+ME_EXPORT int32_t me_mvp_tables_size(int32_t range) {
+    if (range < 1 || range > 31) return ME_EUNSUPPORTED;
+    return MvpLayout(range).total;
+}
+
+ME_EXPORT int me_mvp_tables(const uint32_t* hist, const uint32_t* d1, const uint32_t* d2, int32_t range, double* out,
+                            void* stream) {
+    if (range < 1 || range > 31) return ME_EUNSUPPORTED;
+    if (!hist || !d1 || !d2 || !out) return ME_EINVAL;
+    if (!aligned(hist, 4) || !aligned(d1, 4) || !aligned(d2, 4) || !aligned(out, 8)) return ME_EINVAL;
+    hipLaunchKernelGGL(k_mvp_tables, dim3(1), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), hist, d1, d2,
+                       range, out);
     return launched();
 }
 

@@ -44,21 +44,43 @@ template <int B>
 __host__ __device__ constexpr size_t fs_lds_bytes(int R) {
     const int J = fs_rows_per_item(R);
     const int rows = ((2 * R + 1 + J - 1) / J) * J + B - 1;
-    return (size_t)4 * rows * fs_window_words(B, R) + 4 * 4;
+    return (size_t)4 * rows * fs_window_words(B, R) + 4 * 12;
 }
 
 __device__ __forceinline__ uint32_t fs_key(uint32_t s, int x, int y) {
     return (s << 13) | ((uint32_t)(abs(x) + abs(y)) << 7) | ((uint32_t)(y + 31) << 1) | (x > 0 ? 1u : 0u);
 }
 
+__device__ __forceinline__ void fs_decode(uint32_t k, int& x, int& y) {
+    y = (int)((k >> 1) & 63u) - 31;
+    const int ax = (int)((k >> 7) & 63u) - abs(y);
+    x = (k & 1u) ? ax : -ax;
+}
+
+// Counters of the MVP statistics (§II-C), n = 2R + 1, vector index
+// (y + R) n + (x + R):
+//   hist[n^2]       full-search vectors (Tables II-III, Fig. 3)
+//   d1[9][n^2]      vector given the best point P of the CDS first-step cross
+//                   (Eq. (4)); P index: (x + 2) for (x, 0), x = -2..2, then
+//                   5..8 for (0, -2), (0, -1), (0, 1), (0, 2)
+//   d2[n^2][25]     best point of the central 5x5 square given the vector
+//                   (Eq. (6)); point index (y + 2) 5 + (x + 2)
+struct MvpCounts {
+    uint32_t* hist;
+    uint32_t* d1;
+    uint32_t* d2;
+};
+
 // J candidate rows per item; nt threads per workgroup.  The block rows are
 // taken V at a time (a runtime loop, so that only V rows of the current block
 // are live in scalar registers); each step reads the V + J - 1 reference rows
 // it needs from LDS.
-template <int B, int J>
+// ST: also the minima over the CDS first-step cross (c1) and over the
+// central 5x5 square (c2), with the same keys.
+template <int B, int J, bool ST>
 __device__ __forceinline__ uint32_t fs_items_min(const uint32_t* win, int WD, int G, int items, int R, int MW,
                                                  const uint32_t* cur, int cpw, int lox, int hix, int loy, int hiy,
-                                                 int nt) {
+                                                 int nt, uint32_t& c1, uint32_t& c2) {
     constexpr int K = B / 4;
     constexpr int V = 4;
     constexpr int Q = V + J - 1;
@@ -98,7 +120,13 @@ __device__ __forceinline__ uint32_t fs_items_min(const uint32_t* win, int WD, in
                 const int x = -4 * MW + 4 * g + i;
                 const uint32_t s = (uint32_t)(acc[j] >> (16 * i)) & 0xFFFFu;
                 const bool ok = x >= lox && x <= hix && y >= loy && y <= hiy;
-                best = min(best, ok ? fs_key(s, x, y) : 0xFFFFFFFFu);
+                const uint32_t kk = ok ? fs_key(s, x, y) : 0xFFFFFFFFu;
+                best = min(best, kk);
+                if (ST) {
+                    const bool sq = abs(x) <= 2 && abs(y) <= 2;
+                    c2 = min(c2, sq ? kk : 0xFFFFFFFFu);
+                    c1 = min(c1, sq && (x == 0 || y == 0) ? kk : 0xFFFFFFFFu);
+                }
             }
         }
     }
@@ -107,10 +135,13 @@ __device__ __forceinline__ uint32_t fs_items_min(const uint32_t* win, int WD, in
 
 // One block of one frame pair; all nt threads of the workgroup call it.
 // J = fs_rows_per_item(R) (checked by the caller).
-template <int B, int J>
+// ST: instead of the per-block outputs (mv, sad, nsp may be NULL), count
+// the block in the MVP statistics.
+template <int B, int J, bool ST = false>
 __device__ __forceinline__ void fs_block(uint32_t* smem, const FrameArgs& a, int pair, int bx, int by,
                                          int16_t* __restrict__ mv, uint32_t* __restrict__ sad,
-                                         uint32_t* __restrict__ nsp, uint32_t* __restrict__ sse, int nt) {
+                                         uint32_t* __restrict__ nsp, uint32_t* __restrict__ sse, int nt,
+                                         MvpCounts mc = MvpCounts{nullptr, nullptr, nullptr}) {
     const int R = a.R;
     const int MW = margin_words(R);
     const int G = fs_groups(R);
@@ -132,21 +163,47 @@ __device__ __forceinline__ void fs_block(uint32_t* smem, const FrameArgs& a, int
     const int lox = max(-R, -x0), hix = min(R, a.W - B - x0);
     const int loy = max(-R, -y0), hiy = min(R, a.H - B - y0);
     const int items = G * DG;
-    uint32_t best = fs_items_min<B, J>(win, WD, G, items, R, MW, cur, a.pitch / 4, lox, hix, loy, hiy, nt);
+    uint32_t c1 = 0xFFFFFFFFu, c2 = 0xFFFFFFFFu;
+    uint32_t best =
+        fs_items_min<B, J, ST>(win, WD, G, items, R, MW, cur, a.pitch / 4, lox, hix, loy, hiy, nt, c1, c2);
     // Workgroup minimum: every thread reads the per-wave minima.
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) best = min(best, (uint32_t)__shfl_xor((int)best, o, 64));
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = best;
+    for (int o = 32; o >= 1; o >>= 1) {
+        best = min(best, (uint32_t)__shfl_xor((int)best, o, 64));
+        if (ST) {
+            c1 = min(c1, (uint32_t)__shfl_xor((int)c1, o, 64));
+            c2 = min(c2, (uint32_t)__shfl_xor((int)c2, o, 64));
+        }
+    }
+    if ((threadIdx.x & 63) == 0) {
+        part[threadIdx.x >> 6] = best;
+        part[4 + (threadIdx.x >> 6)] = c1;
+        part[8 + (threadIdx.x >> 6)] = c2;
+    }
     __syncthreads();
     uint32_t k = part[0];
     for (int w = 1; w < nt / 64; ++w) k = min(k, part[w]);
-    const int sgn = (int)(k & 1u);
-    const int y = (int)((k >> 1) & 63u) - 31;
-    const int l1 = (int)((k >> 7) & 63u);
-    const int ax = l1 - abs(y);
-    const int x = sgn ? ax : -ax;
+    int x, y;
+    fs_decode(k, x, y);
     const long long idx = ((long long)pair * a.bh + by) * a.bw + bx;
-    if (threadIdx.x == 0) {
+    if (ST && threadIdx.x == 0) {
+        uint32_t k1 = part[4], k2 = part[8];
+        for (int w = 1; w < nt / 64; ++w) {
+            k1 = min(k1, part[4 + w]);
+            k2 = min(k2, part[8 + w]);
+        }
+        int x1, y1, x2, y2;
+        fs_decode(k1, x1, y1);
+        fs_decode(k2, x2, y2);
+        const int n = 2 * R + 1;
+        const int v = (y + R) * n + (x + R);
+        const int p1 = y1 == 0 ? x1 + 2 : (y1 < 0 ? 7 + y1 : 6 + y1);
+        const int p2 = (y2 + 2) * 5 + (x2 + 2);
+        atomicAdd(&mc.hist[v], 1u);
+        atomicAdd(&mc.d1[p1 * n * n + v], 1u);
+        atomicAdd(&mc.d2[v * 25 + p2], 1u);
+    }
+    if (!ST && threadIdx.x == 0) {
         mv[2 * idx] = (int16_t)x;
         mv[2 * idx + 1] = (int16_t)y;
         sad[idx] = k >> 13;
@@ -183,6 +240,17 @@ __global__ __launch_bounds__(256) void k_fs(FrameArgs a, int16_t* __restrict__ m
     const int by = t % a.bh;
     const int pair = t / a.bh;
     fs_block<B, J>(smem, a, pair, bx, by, mv, sad, nsp, sse, blockDim.x);
+}
+
+template <int B, int J>
+__global__ __launch_bounds__(256) void k_fs_stats(FrameArgs a, MvpCounts mc) {
+    extern __shared__ uint32_t smem[];
+    int t = blockIdx.x;
+    const int bx = t % a.bw;
+    t /= a.bw;
+    const int by = t % a.bh;
+    const int pair = t / a.bh;
+    fs_block<B, J, true>(smem, a, pair, bx, by, nullptr, nullptr, nullptr, nullptr, blockDim.x, mc);
 }
 
 }  // namespace me

@@ -114,6 +114,20 @@ def test_frame_quality_checks():
     assert q(None, None, None, None, 64, 32, 0, 16, None, 0) == me.ME_OK  # nothing to do
 
 
+def test_mvp_checks():
+    base = (P, P, 64, 32, 64, 2048, 1, 16, 7)
+    assert me.me_mvp_stats(*base, None, P, P, 0) == me.ME_EINVAL
+    assert me.me_mvp_stats(*base, P, P, P + 2, 0) == me.ME_EINVAL          # misaligned counter
+    assert me.me_mvp_stats(P, P, 64, 32, 64, 2048, 1, 16, 32, P, P, P, 0) == me.ME_EUNSUPPORTED
+    assert me.me_mvp_stats(P, P, 64, 32, 64, 2048, 0, 16, 7, None, None, None, 0) == me.ME_OK
+    assert me.me_mvp_tables_size(0) == me.ME_EUNSUPPORTED and me.me_mvp_tables_size(32) == me.ME_EUNSUPPORTED
+    n = 15
+    assert me.me_mvp_tables_size(7) == 8 * 8 + 4 * n + 10 + 9 * n * n + 25 * n * n + 50
+    assert me.me_mvp_tables(P, P, P, 7, P + 4, 0) == me.ME_EINVAL          # misaligned output
+    assert me.me_mvp_tables(None, P, P, 7, P, 0) == me.ME_EINVAL
+    assert me.me_mvp_tables(P, P, P, 0, P, 0) == me.ME_EUNSUPPORTED
+
+
 def test_surface_checks():
     assert me.me_dcds_surface(None, None, 1, 7, 1, None, None, P, P, P, 0) == me.ME_EINVAL
     assert me.me_dcds_surface(P, None, -1, 7, 1, None, None, P, P, P, 0) == me.ME_EINVAL
