@@ -278,17 +278,25 @@ ME_EXPORT int me_mvp_stats(const uint8_t* cur, const uint8_t* ref, int32_t width
     if (rc != ME_OK || n_pairs == 0) return rc;
     if (!aligned(hist, 4) || !aligned(d1, 4) || !aligned(d2, 4)) return ME_EINVAL;
     const FrameArgs a = frame_args(cur, ref, width, height, pitch, pair_stride, block, range, 1, 1);
-    const long long grid = (long long)a.bw * a.bh * n_pairs;
+    const long long total = (long long)a.bw * a.bh * n_pairs;
+    if (total > INT32_MAX) return ME_EUNSUPPORTED;
+    // Chunks of consecutive blocks per workgroup, at most 4096 workgroups.
+    const int chunk = (int)((total + 4095) / 4096);
+    const unsigned grid = (unsigned)((total + chunk - 1) / chunk);
     const int nt = fs_threads(range);
     const bool j4 = fs_rows_per_item(range) == 4;
-    const MvpCounts mc{hist, d1, d2};
+    const MvpCounts mc{hist, d1, d2, nullptr};
+    const size_t hash = 4 * (size_t)mvp_hash_words();
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int tb = (int)total;
     if (block == 16) {
-        if (j4) hipLaunchKernelGGL((k_fs_stats<16, 4>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<16>(range), st, a, mc);
-        else hipLaunchKernelGGL((k_fs_stats<16, 1>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<16>(range), st, a, mc);
+        const size_t lds = fs_lds_bytes<16>(range) + hash;
+        if (j4) hipLaunchKernelGGL((k_fs_stats<16, 4>), dim3(grid), dim3(nt), lds, st, a, mc, tb, chunk);
+        else hipLaunchKernelGGL((k_fs_stats<16, 1>), dim3(grid), dim3(nt), lds, st, a, mc, tb, chunk);
     } else {
-        if (j4) hipLaunchKernelGGL((k_fs_stats<8, 4>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<8>(range), st, a, mc);
-        else hipLaunchKernelGGL((k_fs_stats<8, 1>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<8>(range), st, a, mc);
+        const size_t lds = fs_lds_bytes<8>(range) + hash;
+        if (j4) hipLaunchKernelGGL((k_fs_stats<8, 4>), dim3(grid), dim3(nt), lds, st, a, mc, tb, chunk);
+        else hipLaunchKernelGGL((k_fs_stats<8, 1>), dim3(grid), dim3(nt), lds, st, a, mc, tb, chunk);
     }
     return launched();
 }

@@ -69,7 +69,36 @@ struct MvpCounts {
     uint32_t* hist;
     uint32_t* d1;
     uint32_t* d2;
+    uint32_t* lds;  // the workgroup's hash tables (mvp_hash_words words)
 };
+
+// Per-workgroup aggregation of the counters: one open-addressing table of
+// (key, count) per counter array in LDS, filled by thread 0 only, flushed
+// with one global atomic per distinct key.  A key that finds no slot within
+// kMvpProbe probes is counted in global memory directly.
+constexpr int kMvpSlots = 256;
+constexpr int kMvpProbe = 16;
+constexpr uint32_t kMvpEmpty = 0xFFFFFFFFu;
+__host__ __device__ constexpr int mvp_hash_words() { return 3 * 2 * kMvpSlots; }
+
+__device__ __forceinline__ void mvp_add(uint32_t* tab, uint32_t key, uint32_t* global) {
+    uint32_t* keys = tab;
+    uint32_t* cnt = tab + kMvpSlots;
+    const uint32_t h = (key * 2654435761u) >> 24;
+    for (int i = 0; i < kMvpProbe; ++i) {
+        const uint32_t s = (h + i) & (kMvpSlots - 1);
+        if (keys[s] == key) {
+            cnt[s] += 1u;
+            return;
+        }
+        if (keys[s] == kMvpEmpty) {
+            keys[s] = key;
+            cnt[s] = 1u;
+            return;
+        }
+    }
+    atomicAdd(&global[key], 1u);
+}
 
 // J candidate rows per item; nt threads per workgroup.  The block rows are
 // taken V at a time (a runtime loop, so that only V rows of the current block
@@ -199,9 +228,9 @@ __device__ __forceinline__ void fs_block(uint32_t* smem, const FrameArgs& a, int
         const int v = (y + R) * n + (x + R);
         const int p1 = y1 == 0 ? x1 + 2 : (y1 < 0 ? 7 + y1 : 6 + y1);
         const int p2 = (y2 + 2) * 5 + (x2 + 2);
-        atomicAdd(&mc.hist[v], 1u);
-        atomicAdd(&mc.d1[p1 * n * n + v], 1u);
-        atomicAdd(&mc.d2[v * 25 + p2], 1u);
+        mvp_add(mc.lds, (uint32_t)v, mc.hist);
+        mvp_add(mc.lds + 2 * kMvpSlots, (uint32_t)(p1 * n * n + v), mc.d1);
+        mvp_add(mc.lds + 4 * kMvpSlots, (uint32_t)(v * 25 + p2), mc.d2);
     }
     if (!ST && threadIdx.x == 0) {
         mv[2 * idx] = (int16_t)x;
@@ -242,15 +271,34 @@ __global__ __launch_bounds__(256) void k_fs(FrameArgs a, int16_t* __restrict__ m
     fs_block<B, J>(smem, a, pair, bx, by, mv, sad, nsp, sse, blockDim.x);
 }
 
+// Persistent: workgroup w takes blocks [w chunk, (w + 1) chunk) of the
+// flattened (pair, by, bx) space.  LDS: window, reduction scratch, then the
+// hash tables.
 template <int B, int J>
-__global__ __launch_bounds__(256) void k_fs_stats(FrameArgs a, MvpCounts mc) {
+__global__ __launch_bounds__(256) void k_fs_stats(FrameArgs a, MvpCounts mc, int total, int chunk) {
     extern __shared__ uint32_t smem[];
-    int t = blockIdx.x;
-    const int bx = t % a.bw;
-    t /= a.bw;
-    const int by = t % a.bh;
-    const int pair = t / a.bh;
-    fs_block<B, J, true>(smem, a, pair, bx, by, nullptr, nullptr, nullptr, nullptr, blockDim.x, mc);
+    const int R = a.R;
+    const int DG = (2 * R + 1 + J - 1) / J;
+    mc.lds = smem + (DG * J + B - 1) * fs_window_words(B, R) + 12;
+    for (int i = threadIdx.x; i < mvp_hash_words(); i += blockDim.x)
+        mc.lds[i] = (i / kMvpSlots) % 2 == 0 ? kMvpEmpty : 0u;
+    const int lo = blockIdx.x * chunk, hi = min(total, lo + chunk);
+    for (int b = lo; b < hi; ++b) {
+        __syncthreads();
+        int t = b;
+        const int bx = t % a.bw;
+        t /= a.bw;
+        const int by = t % a.bh;
+        const int pair = t / a.bh;
+        fs_block<B, J, true>(smem, a, pair, bx, by, nullptr, nullptr, nullptr, nullptr, blockDim.x, mc);
+    }
+    __syncthreads();
+    uint32_t* const dst[3] = {mc.hist, mc.d1, mc.d2};
+    for (int i = threadIdx.x; i < 3 * kMvpSlots; i += blockDim.x) {
+        const uint32_t* tab = mc.lds + 2 * kMvpSlots * (i / kMvpSlots);
+        const int s = i % kMvpSlots;
+        if (tab[s] != kMvpEmpty) atomicAdd(&dst[i / kMvpSlots][tab[s]], tab[kMvpSlots + s]);
+    }
 }
 
 }  // namespace me
