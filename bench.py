@@ -261,6 +261,7 @@ def main():
                          "dcds always runs")
     ap.add_argument("--sweep", action="store_true",
                     help="time every DCDS kernel configuration (rows per lane x waves per group) and exit")
+    ap.add_argument("--sweep-range", type=int, default=RANGE, help="search range of --sweep")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy 256 MiB device-to-device (a known-size kernel for counter calibration)")
     args = ap.parse_args()
@@ -293,18 +294,24 @@ def main():
         del src, dst
 
     if args.sweep:
+        SR = args.sweep_range
         for B, rpls in ((16, (1, 2, 4)), (8, (1, 2))):
             for rpl in rpls:
-                for wpg in (1, 2, 4):
-                    if me.me_set_config(B, RANGE, (rpl, wpg)) != me.ME_OK:
+                for wpg in (1, 2, 4, 8):
+                    if me.me_set_config(B, SR, (rpl, wpg)) != me.ME_OK:
                         continue
-                    fn = lambda: me.dcds(cur, ref, B, RANGE)  # noqa: E731
-                    fn()
+                    fn = lambda: me.dcds(cur, ref, B, SR)  # noqa: E731
+                    try:
+                        fn()
+                    except me.MEError as e:  # a window too large for LDS
+                        print(json.dumps({"block": B, "rows_per_lane": rpl, "waves_per_group": wpg,
+                                          "range": SR, "error": str(e)}), flush=True)
+                        continue
                     _, ms, _ = time_launches(fn, args.steps, args.warmup, torch)
                     nb = P * (H // B) * (W // B)
-                    print(json.dumps({"block": B, "rows_per_lane": rpl, "waves_per_group": wpg, "ms": ms,
-                                      "mb_per_s": nb / (ms * 1e-3)}), flush=True)
-            me.me_set_config(B, RANGE, None)
+                    print(json.dumps({"block": B, "rows_per_lane": rpl, "waves_per_group": wpg, "range": SR,
+                                      "ms": ms, "mb_per_s": nb / (ms * 1e-3)}), flush=True)
+            me.me_set_config(B, SR, None)
         return
 
     results = {}

@@ -80,7 +80,7 @@ const char *me_status_string(int status);
 /*
  * Kernel configuration of the DCDS searches (me_dcds, me_dcds_ex): how many
  * rows of a block one lane holds (1, 2 or 4 for 16x16 blocks; 1 or 2 for 8x8)
- * and how many waves share one staged reference window (1, 2 or 4; each wave
+ * and how many waves share one staged reference window (1, 2, 4 or 8; each wave
  * takes 64 * rows_per_lane / block blocks side by side).  Results do not
  * depend on it, only speed.  Kept per block size and range class (1-7, 8-15,
  * 16-31) for the process; me_set_config with cfg == NULL restores the

@@ -25,13 +25,33 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp, *srcs]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    """Compiles every source to an object in parallel, then links libme.so."""
+    from concurrent.futures import ThreadPoolExecutor
+    tag = "%d" % os.getpid()
+    objs = []
+    cmds = []
+    for src in SOURCES:
+        obj = os.path.join(CSRC, "%s.%s.o" % (src, tag))
+        objs.append(obj)
+        cmds.append([HIPCC, *[f for f in FLAGS if f != "-shared"], "-c", "-I", os.path.join(ROOT, "include"),
+                     "-I", CSRC, "-o", obj, os.path.join(CSRC, src)])
+    tmp = LIB + ".tmp" + tag
+    try:
+        with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+            for cmd in cmds:
+                if verbose:
+                    print(" ".join(cmd), flush=True)
+            for f in [ex.submit(subprocess.check_call, cmd) for cmd in cmds]:
+                f.result()
+        link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+        if verbose:
+            print(" ".join(link), flush=True)
+        subprocess.check_call(link)
+        os.replace(tmp, LIB)
+    finally:
+        for o in objs + [tmp]:
+            if os.path.exists(o):
+                os.remove(o)
     return LIB
 
 

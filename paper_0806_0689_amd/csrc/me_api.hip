@@ -62,9 +62,15 @@ int launched() { return hipGetLastError() == hipSuccess ? ME_OK : ME_EDEVICE; }
 int range_class(int R) { return R <= 7 ? 0 : (R <= 15 ? 1 : 2); }
 
 std::atomic<int> g_cfg[2][3];  // [block 8/16][range class] = rpl * 16 + wpg; 0 = default
+// Built-in defaults (rows per lane * 16 + waves per group) per block size and
+// range class (1-7, 8-15, 16-31): the fastest measured on MI355X over a
+// 1920x1088 sequence (59 pairs) at ranges 7, 15 and 31.
 int default_cfg(int block, int rc) {
-    (void)rc;
-    return block == 16 ? (2 * 16 + 4) : (2 * 16 + 4);
+    static const int kDefault[2][3] = {
+        {2 * 16 + 4, 2 * 16 + 8, 1 * 16 + 8},   // 8x8 blocks
+        {2 * 16 + 4, 2 * 16 + 8, 2 * 16 + 8},   // 16x16 blocks
+    };
+    return kDefault[block == 16][rc];
 }
 void current_cfg(int block, int rc, int* rpl, int* wpg) {
     int v = g_cfg[block == 16][rc].load(std::memory_order_relaxed);
@@ -74,7 +80,7 @@ void current_cfg(int block, int rc, int* rpl, int* wpg) {
 }
 bool valid_cfg(int block, int rpl, int wpg) {
     const bool r_ok = block == 16 ? (rpl == 1 || rpl == 2 || rpl == 4) : (rpl == 1 || rpl == 2);
-    return r_ok && (wpg == 1 || wpg == 2 || wpg == 4);
+    return r_ok && (wpg == 1 || wpg == 2 || wpg == 4 || wpg == 8);
 }
 int dcds_flags(int32_t algo, const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t pitch,
                int64_t pair_stride) {
@@ -122,7 +128,8 @@ int launch_dcds_wpg(int wpg, const uint8_t* cur, const uint8_t* ref, int32_t wid
 #define ME_ARGS cur, ref, width, height, pitch, pair_stride, n_pairs, range, flags, start, orient, mv, sad, nsp, sse, st
     if (wpg == 1) return launch_dcds_cfg<B, RPL, 1, RMAX>(ME_ARGS);
     if (wpg == 2) return launch_dcds_cfg<B, RPL, 2, RMAX>(ME_ARGS);
-    return launch_dcds_cfg<B, RPL, 4, RMAX>(ME_ARGS);
+    if (wpg == 4) return launch_dcds_cfg<B, RPL, 4, RMAX>(ME_ARGS);
+    return launch_dcds_cfg<B, RPL, 8, RMAX>(ME_ARGS);
 }
 
 template <int B, int RMAX>

@@ -113,7 +113,8 @@ template <int B, int RPL, int RMAX>
 Variant dcds_variant_w(int wpg, int R) {
     if (wpg == 1) return dcds_variant<B, RPL, 1, RMAX>(R);
     if (wpg == 2) return dcds_variant<B, RPL, 2, RMAX>(R);
-    return dcds_variant<B, RPL, 4, RMAX>(R);
+    if (wpg == 4) return dcds_variant<B, RPL, 4, RMAX>(R);
+    return dcds_variant<B, RPL, 8, RMAX>(R);
 }
 
 template <int B, int RMAX>
@@ -288,9 +289,9 @@ ME_EXPORT int me_autotune(const me_job* jobs, int32_t n_jobs, int32_t algo, int3
     float top_ms = 0.f;
     int rc = ME_OK;
     const int rpls[3] = {1, 2, 4};
-    const int wpgs[3] = {1, 2, 4};
+    const int wpgs[4] = {1, 2, 4, 8};
     for (int ri = 0; ri < 3 && rc == ME_OK; ++ri) {
-        for (int wi = 0; wi < 3 && rc == ME_OK; ++wi) {
+        for (int wi = 0; wi < 4 && rc == ME_OK; ++wi) {
             me_config c{rpls[ri], wpgs[wi]};
             if (me_set_config(block, range, &c) != ME_OK) continue;
             int r = batch_launch(jobs, n_jobs, algo, block, range, st);  // warm-up, builds the graph

@@ -42,12 +42,13 @@ struct DcdsGeo {
     static constexpr int MR = RMAX + 2;      // rows above and below the tile
     static constexpr int ML = round_up(MR, 16);              // bytes left of the tile
     static constexpr int NEED = round_up(ML + TW + RMAX + 6, 16) / 4;  // words a row must hold
-    // Row pitch of 32m + 1 words: the lanes of a block read consecutive rows
-    // at one column, so they fall into consecutive banks.  (Giving each lane
-    // adjacent rows would let one ds_read2 fetch both, but spreads a block
-    // over every other bank and nearly doubles the bank conflicts between
-    // the blocks of a wave.)
-    static constexpr int WDW = (NEED + 30) / 32 * 32 + 1;
+    // Odd row pitch: the lanes of a block read consecutive rows at one
+    // column, and an odd pitch puts those 8 or 16 reads in distinct banks.
+    // No wider than needed, so that six tiles fit a CU's LDS at +-15.
+    // (Giving each lane adjacent rows would let one ds_read2 fetch both, but
+    // spreads a block over every other bank and nearly doubles the bank
+    // conflicts between the blocks of a wave.)
+    static constexpr int WDW = NEED | 1;
     static constexpr int WR = TH + 2 * MR;   // LDS rows
     static constexpr int WIN_WORDS = WR * WDW;
     static_assert(L >= 2 && BPW * L == 64, "lanes per block must divide the wave");
@@ -292,8 +293,8 @@ __device__ __forceinline__ void dcds_tile(uint32_t* smem, const FrameArgs& a, in
             ov = orient != nullptr && orient[idx] != 0;
         }
         const SearchOut r = (flags & DCDS_SIMPLIFIED) != 0
-                                ? dcds_search<L, true>(ev, R, bd, bm, g, seeded, sx, sy, ov)
-                                : dcds_search<L, false>(ev, R, bd, bm, g, seeded, sx, sy, ov);
+                                ? dcds_search<L, RMAX, true>(ev, R, bd, bm, g, seeded, sx, sy, ov)
+                                : dcds_search<L, RMAX, false>(ev, R, bd, bm, g, seeded, sx, sy, ov);
         // Optional epilogue: the squared error of the compensated block.
         const uint32_t e = sse ? ev.sse(ev.a00 + __mul24(r.y, G::WDW * 4) + r.x) : 0u;
         if (g == 0) {

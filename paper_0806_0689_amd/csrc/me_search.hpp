@@ -66,7 +66,7 @@ __device__ __forceinline__ uint32_t key(bool valid, uint32_t cost, uint32_t idx)
 // Points outside the candidate set may be evaluated on any finite data; their
 // results are masked here.
 // simplified: Step 4 of DCDS^S; seeded: learned start (sx, sy, orient_v).
-template <int L, bool SIMPLIFIED, class Ev>
+template <int L, int RMAX, bool SIMPLIFIED, class Ev>
 __device__ SearchOut dcds_search(const Ev& ev, int R, const Bounds& bd, uint32_t* bm, int g, bool seeded, int sx,
                                  int sy, bool orient_v) {
     static_assert(L == 4 || L == 8 || L == 16, "group of 4, 8 or 16 lanes");
@@ -80,10 +80,17 @@ __device__ SearchOut dcds_search(const Ev& ev, int R, const Bounds& bd, uint32_t
         if (act) (void)atomicOr(&bm[k >> 5], 1u << (k & 31));
     };
     // NSP: the number of bits set (the group's own LDS operations complete in
-    // order, so every mark is visible here).
+    // order, so every mark is visible here).  RMAX bounds R, so the word loop
+    // has a fixed trip count.
     auto count = [&]() -> uint32_t {
+        constexpr int WMAX = ((2 * RMAX + 1) * (2 * RMAX + 1) + 31) / 32;
+        const int words = (S * S + 31) / 32;
         uint32_t n = 0;
-        for (int i = g; i < (S * S + 31) / 32; i += L) n += __popc(bm[i]);
+#pragma unroll
+        for (int j = 0; j < (WMAX + L - 1) / L; ++j) {
+            const int i = g + j * L;
+            if (i < words) n += __popc(bm[i]);
+        }
         return group_sum<L>(n);
     };
 

@@ -163,7 +163,8 @@ def test_config_set_get_and_checks():
     assert me.me_get_config(16, 15) == d16
     assert me.me_set_config(8, 15, (4, 2)) == me.ME_EUNSUPPORTED   # 8x8 blocks: 1 or 2 rows per lane
     assert me.me_set_config(16, 15, (3, 2)) == me.ME_EUNSUPPORTED
-    assert me.me_set_config(16, 15, (2, 8)) == me.ME_EUNSUPPORTED
+    assert me.me_set_config(16, 15, (2, 16)) == me.ME_EUNSUPPORTED
+    assert me.me_set_config(16, 15, (2, 8)) == me.ME_OK
     assert me.me_set_config(12, 15, (2, 2)) == me.ME_EUNSUPPORTED
     assert me.me_set_config(16, 0, (2, 2)) == me.ME_EUNSUPPORTED
     assert me.lib().me_get_config(16, 15, None) == me.ME_EINVAL

@@ -94,7 +94,7 @@ def test_autotune_and_cache_roundtrip(streams, tmp_path):
     try:
         cfg, ms = me.autotune(pairs, 16, 15, reps=2)
         say("autotune best", cfg, ms)
-        assert cfg[0] in (1, 2, 4) and cfg[1] in (1, 2, 4) and ms > 0
+        assert cfg[0] in (1, 2, 4) and cfg[1] in (1, 2, 4, 8) and ms > 0
         assert me.me_get_config(16, 15) == cfg
         got = me.batch(pairs, 16, 15)
         for (cur, ref), g in zip(pairs, got):

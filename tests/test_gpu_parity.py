@@ -213,8 +213,8 @@ def test_random_surfaces_vs_oracle(R):
                 assert (tuple(gmv[i]), gc[i], gn[i]) == (emv, ec, en), (R, algo, seeded, i)
 
 
-CONFIGS16 = [(r, w) for r in (1, 2, 4) for w in (1, 2, 4)]
-CONFIGS8 = [(r, w) for r in (1, 2) for w in (1, 2, 4)]
+CONFIGS16 = [(r, w) for r in (1, 2, 4) for w in (1, 2, 4, 8)]
+CONFIGS8 = [(r, w) for r in (1, 2) for w in (1, 2, 4, 8)]
 
 
 @pytest.mark.parametrize("B,cfg", [(16, c) for c in CONFIGS16] + [(8, c) for c in CONFIGS8])
