@@ -34,10 +34,8 @@ constexpr int kExposedCout[4] = {16, 32, 32, 3};
 
 __host__ __device__ constexpr int pad16(int v) { return (v + 15) / 16 * 16; }
 
-__device__ __forceinline__ uint16_t f2bf(float f) {
-    const uint32_t u = __float_as_uint(f);
-    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
-}
+// Round to bfloat16, nearest even (v_cvt_pk_bf16_f32).
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 __device__ __forceinline__ v4s as_v4s(uint2 v) {
@@ -369,6 +367,232 @@ __global__ __launch_bounds__(256) void k_head_export(const float* __restrict__ h
     out[3 * i] = head[4 * i];
     out[3 * i + 1] = head[4 * i + 1];
     out[3 * i + 2] = head[4 * i + 2];
+}
+
+
+// ---------------------------------------------------------------------------
+// Fused inference: all four layers for a tile of kTB x kTB blocks, with every
+// activation in LDS, then the start-vector decode.  Each output takes exactly
+// the operands and the k-step order of k_downdiff + k_conv_fwd + k_head_decode
+// (same bf16 values, same 16-wide MFMA steps in the same order, zero padding
+// outside each layer's image), so the two paths give identical results.
+//
+// Tile sides (with the halo each 3x3 layer needs): L3 kN3 = kTB + 2, L2
+// kN2 = 2 kN3 + 1, L1 kN1 = 2 kN2 + 1, input kN0 = kN1 + 2.  Per-pixel
+// pitches (in bf16) pad the NHWC rows so that the 16 pixels of an MFMA
+// operand fall into different LDS banks.  Persistent: one workgroup per CU
+// stages the weights once (rows padded by 4 for the same reason) and walks
+// the tiles.
+// ---------------------------------------------------------------------------
+constexpr int kTB = 8;
+constexpr int kN3 = kTB + 2, kN2 = 2 * kN3 + 1, kN1 = 2 * kN2 + 1, kN0 = kN1 + 2;
+constexpr int kP0 = 4, kP1 = 20, kP2 = 40, kP3 = 40;  // pixel pitches
+constexpr int kSz0 = kN0 * kN0 * kP0, kSz1 = kN1 * kN1 * kP1, kSz2 = kN2 * kN2 * kP2, kSz3 = kN3 * kN3 * kP3;
+constexpr int kRegC = kSz0 > kSz3 ? kSz0 : kSz3;
+// Weights in LDS: layer l as [COUT][KP + 4] bf16.
+__host__ __device__ constexpr int wrow(int l) { return pad16(9 * kLayers[l].cin) + 4; }
+__host__ __device__ constexpr int wsize(int l) { return kLayers[l].cout * wrow(l); }
+constexpr int kWOff1 = wsize(0), kWOff2 = kWOff1 + wsize(1), kWOff3 = kWOff2 + wsize(2), kWAll = kWOff3 + wsize(3);
+constexpr int kBias = 16 + 32 + 32 + 4;
+constexpr size_t kFusedLds =
+    2 * (size_t)(kSz1 + kSz2 + kRegC + kWAll) + 4 * (size_t)(4 * kTB * kTB) + 4 * (size_t)kBias;
+constexpr int kFusedThreads = 512;
+
+// One 3x3 layer from an LDS tile to an LDS tile (or, for the head, to the
+// head buffer).  NI/NO: input/output tile sides; PI/PO: pixel pitches; W:
+// this layer's weights in LDS ([COUT][KP + 4]); (oy0, ox0): output tile
+// origin in its layer's grid of Ho x Wo (outputs outside are written as 0,
+// the next layer's padding).  A lane's operand address is a per-tile base
+// plus a per-k-step offset fixed for the layer (a compile-time constant
+// beyond the lane's channel group when CIN >= 16).
+template <int CIN, int COUT, int S, int NI, int NO, int PI, int PO, bool RELU, bool HEAD>
+__device__ __forceinline__ void conv_tile(const uint16_t* in, uint16_t* out, float* head, const uint16_t* W,
+                                          const float* bias, int oy0, int ox0, int Ho, int Wo) {
+    constexpr int KP = pad16(9 * CIN);
+    constexpr int KS = KP / 16;
+    constexpr int NT = (COUT + 15) / 16;
+    constexpr int M = NO * NO;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int m = lane & 15, kq = lane >> 4;
+    v4s b[KS][NT];
+    int aoff[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        int tap, ci;
+        if constexpr (CIN >= 16) {
+            tap = 16 * ks / CIN;
+            ci = 16 * ks % CIN + 4 * kq;
+        } else {
+            tap = (16 * ks + 4 * kq) / CIN;
+            ci = (16 * ks + 4 * kq) % CIN;
+        }
+        // Padded reduction indices (tap >= 9, layer 1 only) read the pixel
+        // itself: finite data against zero weights, which adds exact zeros.
+        aoff[ks] = tap < 9 ? ((tap / 3) * NI + tap % 3) * PI + ci : ci;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int n = t * 16 + m;
+            uint2 bv = make_uint2(0u, 0u);
+            if (n < COUT) bv = *reinterpret_cast<const uint2*>(W + n * (KP + 4) + ks * 16 + 4 * kq);
+            b[ks][t] = as_v4s(bv);
+        }
+    }
+    float bn[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) bn[t] = t * 16 + m < COUT ? bias[t * 16 + m] : 0.f;
+    const bool interior = oy0 >= 0 && ox0 >= 0 && oy0 + NO <= Ho && ox0 + NO <= Wo;
+    for (int tile = wave; tile * 16 < M; tile += nw) {
+        // This lane's A row (output pixel); rows past the tile read the last
+        // pixel and are never stored.
+        const int pa = min(tile * 16 + m, M - 1);
+        const int ay = pa / NO, ax = pa - ay * NO;
+        const uint16_t* ab = in + (S * ay * NI + S * ax) * PI;
+        v4f acc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const v4s a = as_v4s(*reinterpret_cast<const uint2*>(ab + aoff[ks]));
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[ks][t], acc[t], 0, 0, 0);
+        }
+        const int p0 = tile * 16 + 4 * kq;
+        const bool full = tile * 16 + 16 <= M;  // uniform: every row of this tile is an output
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int n = t * 16 + m;
+            if (n >= COUT) continue;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float v = acc[t][i] + bn[t];
+                if (RELU) v = fmaxf(v, 0.f);
+                const int po = p0 + i;
+                if (full && (HEAD || interior)) {
+                    if (HEAD) head[po * 4 + n] = v;
+                    else out[po * PO + n] = f2bf(v);
+                } else if (po < M) {
+                    if (HEAD) {
+                        head[po * 4 + n] = v;
+                    } else {
+                        const int gy = oy0 + po / NO, gx = ox0 + po % NO;
+                        const bool inside = gy >= 0 && gy < Ho && gx >= 0 && gx < Wo;
+                        out[po * PO + n] = inside ? f2bf(v) : (uint16_t)0;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// The input tile (4x4 box means of cur and ref, as k_downdiff; 0 outside):
+// each work item is one row of 4 adjacent input pixels, whose 32 frame
+// words are all requested before any is used.
+__device__ __forceinline__ void input_tile(uint16_t* rc, const uint8_t* cp, const uint8_t* rp, int pitch, int y0,
+                                           int x0, int H4, int W4) {
+    constexpr int G = (kN0 + 3) / 4;  // groups of 4 pixels per row
+    for (int it = threadIdx.x; it < kN0 * G; it += blockDim.x) {
+        const int i = it / G, q = it % G;
+        const int gy = y0 + i;
+        const bool yin = gy >= 0 && gy < H4;
+        uint32_t c[4][4], r[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int gx = x0 + 4 * q + u;
+            const bool in = yin && gx >= 0 && gx < W4 && 4 * q + u < kN0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                c[u][j] = in ? *reinterpret_cast<const uint32_t*>(cp + (size_t)(4 * gy + j) * pitch + 4 * gx) : 0u;
+                r[u][j] = in ? *reinterpret_cast<const uint32_t*>(rp + (size_t)(4 * gy + j) * pitch + 4 * gx) : 0u;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int jx = 4 * q + u;
+            if (jx >= kN0) continue;
+            const int gx = x0 + jx;
+            uint2 o = make_uint2(0u, 0u);
+            if (yin && gx >= 0 && gx < W4) {
+                uint32_t sc = 0, sr = 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    sc = __builtin_amdgcn_sad_u8(c[u][j], 0u, sc);
+                    sr = __builtin_amdgcn_sad_u8(r[u][j], 0u, sr);
+                }
+                const float mc = (float)sc * (1.0f / 16.0f), mr = (float)sr * (1.0f / 16.0f);
+                o.x = (uint32_t)f2bf((mc - mr) * (1.0f / 32.0f)) |
+                      ((uint32_t)f2bf((mc - 128.0f) * (1.0f / 64.0f)) << 16);
+            }
+            *reinterpret_cast<uint2*>(rc + (i * kN0 + jx) * kP0) = o;
+        }
+    }
+}
+
+// grid: min(tiles, CUs) workgroups of kFusedThreads threads, kFusedLds bytes.
+// wf/bias: the packed layer weights ([COUT][KP]) and biases.
+__global__ __launch_bounds__(kFusedThreads) void k_proposer_infer(
+    const uint8_t* __restrict__ cur, const uint8_t* __restrict__ ref, int pitch, long long pair_stride, int Hb, int Wb,
+    int n_pairs, const uint16_t* __restrict__ wf0, const uint16_t* __restrict__ wf1,
+    const uint16_t* __restrict__ wf2, const uint16_t* __restrict__ wf3, const float* __restrict__ b0,
+    const float* __restrict__ b1, const float* __restrict__ b2, const float* __restrict__ b3, int R,
+    int16_t* __restrict__ start, uint8_t* __restrict__ orient) {
+    extern __shared__ uint16_t lds[];
+    uint16_t* l1 = lds;
+    uint16_t* l2 = l1 + kSz1;
+    uint16_t* rc = l2 + kSz2;  // input tile, then the L3 tile
+    uint16_t* wl = rc + kRegC;
+    float* head = reinterpret_cast<float*>(wl + kWAll);
+    float* bl = head + 4 * kTB * kTB;
+    // Weights and biases, once.
+    {
+        const uint16_t* src[4] = {wf0, wf1, wf2, wf3};
+        const int off[4] = {0, kWOff1, kWOff2, kWOff3};
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            const int kp = pad16(9 * kLayers[l].cin), rows = kLayers[l].cout;
+            for (int i = threadIdx.x; i < rows * (kp + 4); i += blockDim.x) {
+                const int n = i / (kp + 4), k = i % (kp + 4);
+                wl[off[l] + i] = k < kp ? src[l][n * kp + k] : (uint16_t)0;
+            }
+        }
+        for (int i = threadIdx.x; i < kBias; i += blockDim.x)
+            bl[i] = i < 16 ? b0[i] : i < 48 ? b1[i - 16] : i < 80 ? b2[i - 48] : b3[i - 80];
+    }
+    const int H4 = 4 * Hb, W4 = 4 * Wb, H8 = 2 * Hb, W8 = 2 * Wb;
+    const int tx = (Wb + kTB - 1) / kTB, ty = (Hb + kTB - 1) / kTB;
+    const int total = tx * ty * n_pairs;
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const int p = t / (tx * ty), r = t % (tx * ty);
+        const int bx0 = (r % tx) * kTB, by0 = (r / tx) * kTB;
+        // Tile origins per layer (grid coordinates of local (0, 0)).
+        const int y3 = by0 - 1, x3 = bx0 - 1;
+        const int y2 = 2 * y3 - 1, x2 = 2 * x3 - 1;
+        const int y1 = 2 * y2 - 1, x1 = 2 * x2 - 1;
+        __syncthreads();  // the previous tile's readers of every buffer are done
+        input_tile(rc, cur + (long long)p * pair_stride, ref + (long long)p * pair_stride, pitch, y1 - 1, x1 - 1, H4,
+                   W4);
+        __syncthreads();
+        conv_tile<4, 16, 1, kN0, kN1, kP0, kP1, true, false>(rc, l1, nullptr, wl, bl, y1, x1, H4, W4);
+        __syncthreads();
+        conv_tile<16, 32, 2, kN1, kN2, kP1, kP2, true, false>(l1, l2, nullptr, wl + kWOff1, bl + 16, y2, x2, H8, W8);
+        __syncthreads();
+        conv_tile<32, 32, 2, kN2, kN3, kP2, kP3, true, false>(l2, rc, nullptr, wl + kWOff2, bl + 48, y3, x3, Hb, Wb);
+        __syncthreads();
+        // Head over the kTB x kTB blocks: local L3 (1 + i, 1 + j) is block (by0 + i, bx0 + j).
+        conv_tile<32, 4, 1, kN3, kTB, kP3, 4, false, true>(rc, nullptr, head, wl + kWOff3, bl + 80, by0, bx0, Hb, Wb);
+        __syncthreads();
+        if (threadIdx.x < kTB * kTB) {
+            const int i = threadIdx.x / kTB, j = threadIdx.x % kTB;
+            const int by = by0 + i, bx = bx0 + j;
+            if (by < Hb && bx < Wb) {
+                const float* h = head + threadIdx.x * 4;
+                const long long o = ((long long)p * Hb + by) * Wb + bx;
+                const float u = rintf(h[0] * 8.f), v = rintf(h[1] * 8.f);
+                start[2 * o] = (int16_t)fminf(fmaxf(u, (float)-R), (float)R);
+                start[2 * o + 1] = (int16_t)fminf(fmaxf(v, (float)-R), (float)R);
+                orient[o] = h[2] > 0.f ? 1 : 0;
+            }
+        }
+    }
 }
 
 }  // namespace cnn

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <random>
 #include <vector>
@@ -389,10 +390,30 @@ ME_EXPORT int me_proposer_infer(me_proposer* p, const uint8_t* cur, const uint8_
     if (n_pairs == 0) return ME_OK;
     if (!start || !orient) return ME_EINVAL;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    rc = forward(p, cur, ref, width, height, pitch, pair_stride, n_pairs, st);
-    if (rc) return rc;
-    const int n = n_pairs * (height / 16) * (width / 16);
-    hipLaunchKernelGGL(k_head_decode, dim3(cdiv(n, 256)), dim3(256), 0, st, p->head, n, range,
+    // One fused launch: every layer of a tile of blocks stays in LDS (the
+    // results equal forward() followed by the head decode).
+    static std::atomic<int> raised{0};
+    if (!raised.load()) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_proposer_infer),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedLds) != hipSuccess)
+            return ME_EDEVICE;
+        raised.store(1);
+    }
+    const Offsets oi = internal_offsets();
+    const int Hb = height / 16, Wb = width / 16;
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return ME_EDEVICE;
+        cus = prop.multiProcessorCount;
+    }
+    const long long tiles = (long long)cdiv(Wb, kTB) * cdiv(Hb, kTB) * n_pairs;
+    if (tiles > INT32_MAX) return ME_EUNSUPPORTED;
+    const unsigned grid = (unsigned)std::min<long long>(tiles, cus);
+    hipLaunchKernelGGL(k_proposer_infer, dim3(grid), dim3(kFusedThreads), kFusedLds, st, cur, ref, pitch,
+                       (long long)pair_stride, Hb, Wb, n_pairs, p->wf[0], p->wf[1], p->wf[2], p->wf[3],
+                       p->w + oi.b[0], p->w + oi.b[1], p->w + oi.b[2], p->w + oi.b[3], range,
                        reinterpret_cast<int16_t*>(start), orient);
     return launched();
 }
