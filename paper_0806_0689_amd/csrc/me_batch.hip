@@ -13,6 +13,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <string>
@@ -32,6 +33,7 @@ constexpr int kMaxJobs = 4096;
 constexpr int kSlots = 2;
 
 enum { KIND_DCDS = 1, KIND_FS = 2 };
+constexpr size_t kStaticLdsReserve = 1024;  // static LDS of the persistent kernels (bytes, upper bound)
 
 // kind, B, rpl, wpg, range class, kernel, threads, lds, cap: everything a captured graph bakes in.
 using GraphKey = std::tuple<int, int, int, int, int, const void*, int, size_t, int>;
@@ -199,7 +201,7 @@ int batch_launch(const me_job* jobs, int32_t n_jobs, int32_t algo, int32_t block
     if (tab.empty()) return ME_OK;
 
     const Variant v = pick_variant(kind, block, rpl, wpg, range);
-    if (v.lds > kMaxLds) return ME_EUNSUPPORTED;
+    if (v.lds > kMaxLds - kStaticLdsReserve) return ME_EUNSUPPORTED;
 
     std::lock_guard<std::mutex> lock(g_batch.mu);
     int rc = ensure_state();
@@ -218,12 +220,19 @@ int batch_launch(const me_job* jobs, int32_t n_jobs, int32_t algo, int32_t block
     while (cap < (int)tab.size()) cap *= 2;
     const size_t table_bytes = batch_table_bytes(cap);
 
-    if (v.lds > 65536 &&
-        hipFuncSetAttribute(v.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds) != hipSuccess)
+    // The persistent kernels also hold a little static LDS (the grabbed tile
+    // index): their dynamic limit leaves room for it.
+    if (v.lds > 65536 && hipFuncSetAttribute(v.fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)(kMaxLds - kStaticLdsReserve)) != hipSuccess)
         return ME_EUNSUPPORTED;
+    // Workgroups resident per CU: the runtime's occupancy answer, bounded by
+    // the LDS each one takes (the query can report 0 for windows above 64 KiB
+    // even after the limit was raised; the LDS bound is then what applies).
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, v.fn, v.threads, v.lds) != hipSuccess || per_cu < 1)
-        return ME_EUNSUPPORTED;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, v.fn, v.threads, v.lds) != hipSuccess) per_cu = 0;
+    const int by_lds = (int)(kMaxLds / std::max<size_t>(v.lds, 1));
+    if (per_cu < 1) per_cu = std::min(by_lds, 2048 / v.threads);
+    if (per_cu < 1) return ME_EUNSUPPORTED;
     const unsigned grid = (unsigned)(per_cu * g_batch.cus);
 
     const GraphKey key{kind, block, rpl, wpg, range_class(range), v.fn, v.threads, v.lds, cap};

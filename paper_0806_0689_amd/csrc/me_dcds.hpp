@@ -1,8 +1,9 @@
 // DCDS over frame pairs.
 //
 // Layout.  A workgroup of WPG waves owns a tile of BPW x WPG blocks: each wave
-// takes BPW = 64 / L blocks side by side, each block L = B / RPL lanes, lane
-// g the rows g, g + L, ... of its block (each row's B/4 words in VGPRs).  The
+// takes BPW = 64 / L blocks side by side, each block L = B / RPL lanes, each
+// lane RPL rows of its block, at most 4 apart (each row's B/4 words in
+// VGPRs; FrameEval gives the mapping).  The
 // tile's reference window, widened by RMAX + 2 rows and at least as many
 // columns on every side (so every point a pattern can reach from a valid
 // centre is in LDS), is staged once; each block keeps its visited-point bitmap
@@ -36,6 +37,7 @@ template <int B, int RPL, int WPG, int RMAX>
 struct DcdsGeo {
     static constexpr int K = B / 4;          // words per block row
     static constexpr int L = B / RPL;        // lanes per block
+    static constexpr int D = L < 4 ? L : 4;  // rows between a lane's rows
     static constexpr int BPW = 64 / L;       // blocks per wave
     static constexpr int TW = BPW * B;       // tile width (pixels)
     static constexpr int TH = WPG * B;       // tile height
@@ -95,15 +97,24 @@ __device__ __forceinline__ void stage(uint32_t* win, const uint8_t* frame, int W
     }
 }
 
-// Lane g of a block holds rows g, g + L, ..., g + (RPL - 1) L of the block.
-// A point's address is the LDS byte offset of its reference pixel for this
-// lane's first row: a00 + y * ROWB + x.
+// Lane g of a block holds rows row0(g) + j D, j < RPL, D = min(L, 4):
+// rows at most 4 apart, so one ds_read2 fetches a word of two of them, and
+// the first rows of a block's lanes, (g mod D) + RPL D (g / D), are distinct
+// mod 32 for an odd pitch.  A point's address is the LDS byte offset of its
+// reference pixel for this lane's first row: a00 + y * ROWB + x.
+template <int RPL, int L>
+__host__ __device__ constexpr int row0(int g) {
+    constexpr int D = L < 4 ? L : 4;
+    return g % D + RPL * D * (g / D);
+}
+
 template <int B, int RPL, int WDW>
 struct FrameEval {
     static constexpr int K = B / 4;
     static constexpr int L = B / RPL;
+    static constexpr int D = L < 4 ? L : 4;
     static constexpr int ROWB = WDW * 4;
-    static constexpr int JW = L * WDW;  // words between a lane's rows
+    static constexpr int JW = D * WDW;  // words between a lane's rows
     int a00;             // address of point (0, 0): an LDS byte address
     uint32_t cur[RPL][K];
 
@@ -258,12 +269,12 @@ __device__ __forceinline__ void dcds_tile(uint32_t* smem, const FrameArgs& a, in
     for (int i = g; i < BMW; i += L) bm[i] = 0u;
 
     FrameEval<B, RPL, G::WDW> ev;
-    ev.a00 = (int)lds_offset(win) + (G::MR + wave * B + g) * (G::WDW * 4) + G::ML + b * B;
+    ev.a00 = (int)lds_offset(win) + (G::MR + wave * B + row0<RPL, L>(g)) * (G::WDW * 4) + G::ML + b * B;
     const int x0 = bx * B, y0 = by * B;
     if (exists) {
 #pragma unroll
         for (int j = 0; j < RPL; ++j) {
-            const uint8_t* row = curf + (size_t)(y0 + g + j * L) * a.pitch + x0;
+            const uint8_t* row = curf + (size_t)(y0 + row0<RPL, L>(g) + j * G::D) * a.pitch + x0;
             if (K == 4 && vec) {
                 const uint4 v = *reinterpret_cast<const uint4*>(row);
                 ev.cur[j][0] = v.x;
@@ -292,9 +303,12 @@ __device__ __forceinline__ void dcds_tile(uint32_t* smem, const FrameArgs& a, in
             sy = start[2 * idx + 1];
             ov = orient != nullptr && orient[idx] != 0;
         }
-        const SearchOut r = (flags & DCDS_SIMPLIFIED) != 0
-                                ? dcds_search<L, RMAX, true>(ev, R, bd, bm, g, seeded, sx, sy, ov)
-                                : dcds_search<L, RMAX, false>(ev, R, bd, bm, g, seeded, sx, sy, ov);
+        const bool simp = (flags & DCDS_SIMPLIFIED) != 0;
+        const SearchOut r =
+            seeded ? (simp ? dcds_search<L, RMAX, true, true>(ev, R, bd, bm, g, sx, sy, ov)
+                           : dcds_search<L, RMAX, false, true>(ev, R, bd, bm, g, sx, sy, ov))
+                   : (simp ? dcds_search<L, RMAX, true, false>(ev, R, bd, bm, g, sx, sy, ov)
+                           : dcds_search<L, RMAX, false, false>(ev, R, bd, bm, g, sx, sy, ov));
         // Optional epilogue: the squared error of the compensated block.
         const uint32_t e = sse ? ev.sse(ev.a00 + __mul24(r.y, G::WDW * 4) + r.x) : 0u;
         if (g == 0) {

@@ -65,10 +65,10 @@ __device__ __forceinline__ uint32_t key(bool valid, uint32_t cost, uint32_t idx)
 // HCSP order: centre, -1, +1, -2, +2 along the arm, -1, +1 across it.
 // Points outside the candidate set may be evaluated on any finite data; their
 // results are masked here.
-// simplified: Step 4 of DCDS^S; seeded: learned start (sx, sy, orient_v).
-template <int L, int RMAX, bool SIMPLIFIED, class Ev>
-__device__ SearchOut dcds_search(const Ev& ev, int R, const Bounds& bd, uint32_t* bm, int g, bool seeded, int sx,
-                                 int sy, bool orient_v) {
+// SIMPLIFIED: Step 4 of DCDS^S; SEEDED: learned start (sx, sy, orient_v).
+template <int L, int RMAX, bool SIMPLIFIED, bool SEEDED, class Ev>
+__device__ SearchOut dcds_search(const Ev& ev, int R, const Bounds& bd, uint32_t* bm, int g, int sx, int sy,
+                                 bool orient_v) {
     static_assert(L == 4 || L == 8 || L == 16, "group of 4, 8 or 16 lanes");
     const int S = 2 * R + 1;      // bitmap row length
     const int k00 = R * S + R;    // bitmap index of the origin
@@ -95,7 +95,7 @@ __device__ SearchOut dcds_search(const Ev& ev, int R, const Bounds& bd, uint32_t
     };
 
     uint32_t c7[7];
-    if (seeded) {
+    if constexpr (SEEDED) {
         // Learned start: probe the origin and the (clamped) start; lane 0
         // marks the origin, lane 1 the start.
         sx = clampi(sx, bd.lox, bd.hix);

@@ -78,8 +78,11 @@ __global__ __launch_bounds__(256) void k_dcds_surface(const int32_t* __restrict_
         sy = start[2 * s + 1];
         ov = orient != nullptr && orient[s] != 0;
     }
-    const SearchOut r = simplified ? dcds_search<L, 31, true>(ev, R, bd, bm, g, seeded, sx, sy, ov)
-                                   : dcds_search<L, 31, false>(ev, R, bd, bm, g, seeded, sx, sy, ov);
+    const SearchOut r =
+        seeded ? (simplified ? dcds_search<L, 31, true, true>(ev, R, bd, bm, g, sx, sy, ov)
+                             : dcds_search<L, 31, false, true>(ev, R, bd, bm, g, sx, sy, ov))
+               : (simplified ? dcds_search<L, 31, true, false>(ev, R, bd, bm, g, sx, sy, ov)
+                             : dcds_search<L, 31, false, false>(ev, R, bd, bm, g, sx, sy, ov));
     if (g == 0) {
         mv[2 * s] = (int16_t)r.x;
         mv[2 * s + 1] = (int16_t)r.y;
