@@ -396,7 +396,21 @@ constexpr int kWOff1 = wsize(0), kWOff2 = kWOff1 + wsize(1), kWOff3 = kWOff2 + w
 constexpr int kBias = 16 + 32 + 32 + 4;
 constexpr size_t kFusedLds =
     2 * (size_t)(kSz1 + kSz2 + kRegC + kWAll) + 4 * (size_t)(4 * kTB * kTB) + 4 * (size_t)kBias;
-constexpr int kFusedThreads = 512;
+#ifndef ME_PROP_THREADS
+#define ME_PROP_THREADS 1024
+#endif
+#ifndef ME_PROP_U1
+#define ME_PROP_U1 1
+#endif
+#ifndef ME_PROP_U2
+#define ME_PROP_U2 1
+#endif
+#ifndef ME_PROP_U3
+#define ME_PROP_U3 1
+#endif
+constexpr int kFusedThreads = ME_PROP_THREADS;
+// M-tiles per wave iteration in layers 1-3.
+constexpr int kU1 = ME_PROP_U1, kU2 = ME_PROP_U2, kU3 = ME_PROP_U3;
 
 // One 3x3 layer from an LDS tile to an LDS tile (or, for the head, to the
 // head buffer).  NI/NO: input/output tile sides; PI/PO: pixel pitches; W:
@@ -405,7 +419,7 @@ constexpr int kFusedThreads = 512;
 // the next layer's padding).  A lane's operand address is a per-tile base
 // plus a per-k-step offset fixed for the layer (a compile-time constant
 // beyond the lane's channel group when CIN >= 16).
-template <int CIN, int COUT, int S, int NI, int NO, int PI, int PO, bool RELU, bool HEAD>
+template <int CIN, int COUT, int S, int NI, int NO, int PI, int PO, bool RELU, bool HEAD, int U>
 __device__ __forceinline__ void conv_tile(const uint16_t* in, uint16_t* out, float* head, const uint16_t* W,
                                           const float* bias, int oy0, int ox0, int Ho, int Wo) {
     constexpr int KP = pad16(9 * CIN);
@@ -441,42 +455,56 @@ __device__ __forceinline__ void conv_tile(const uint16_t* in, uint16_t* out, flo
 #pragma unroll
     for (int t = 0; t < NT; ++t) bn[t] = t * 16 + m < COUT ? bias[t * 16 + m] : 0.f;
     const bool interior = oy0 >= 0 && ox0 >= 0 && oy0 + NO <= Ho && ox0 + NO <= Wo;
-    for (int tile = wave; tile * 16 < M; tile += nw) {
-        // This lane's A row (output pixel); rows past the tile read the last
-        // pixel and are never stored.
-        const int pa = min(tile * 16 + m, M - 1);
-        const int ay = pa / NO, ax = pa - ay * NO;
-        const uint16_t* ab = in + (S * ay * NI + S * ax) * PI;
-        v4f acc[NT];
+    // Each wave takes U M-tiles at a time: their MFMA chains are independent,
+    // so the operand reads of one overlap the products of the others.
+    for (int tile0 = wave * U; tile0 * 16 < M; tile0 += nw * U) {
+        // A lane's A row (output pixel); rows past the tile, and tiles past
+        // the layer, read the last pixel and are never stored.
+        const uint16_t* ab[U];
+        v4f acc[U][NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int u = 0; u < U; ++u) {
+            const int pa = min((tile0 + u) * 16 + m, M - 1);
+            const int ay = pa / NO, ax = pa - ay * NO;
+            ab[u] = in + (S * ay * NI + S * ax) * PI;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[u][t] = v4f{0.f, 0.f, 0.f, 0.f};
+        }
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            const v4s a = as_v4s(*reinterpret_cast<const uint2*>(ab + aoff[ks]));
+            v4s a[U];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[ks][t], acc[t], 0, 0, 0);
+            for (int u = 0; u < U; ++u) a[u] = as_v4s(*reinterpret_cast<const uint2*>(ab[u] + aoff[ks]));
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    acc[u][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[u], b[ks][t], acc[u][t], 0, 0, 0);
         }
-        const int p0 = tile * 16 + 4 * kq;
-        const bool full = tile * 16 + 16 <= M;  // uniform: every row of this tile is an output
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const int n = t * 16 + m;
-            if (n >= COUT) continue;
+        for (int u = 0; u < U; ++u) {
+            const int p0 = (tile0 + u) * 16 + 4 * kq;
+            const bool full = (tile0 + u) * 16 + 16 <= M;  // uniform: every row of this tile is an output
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                float v = acc[t][i] + bn[t];
-                if (RELU) v = fmaxf(v, 0.f);
-                const int po = p0 + i;
-                if (full && (HEAD || interior)) {
-                    if (HEAD) head[po * 4 + n] = v;
-                    else out[po * PO + n] = f2bf(v);
-                } else if (po < M) {
-                    if (HEAD) {
-                        head[po * 4 + n] = v;
-                    } else {
-                        const int gy = oy0 + po / NO, gx = ox0 + po % NO;
-                        const bool inside = gy >= 0 && gy < Ho && gx >= 0 && gx < Wo;
-                        out[po * PO + n] = inside ? f2bf(v) : (uint16_t)0;
+            for (int t = 0; t < NT; ++t) {
+                const int n = t * 16 + m;
+                if (n >= COUT) continue;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    float v = acc[u][t][i] + bn[t];
+                    if (RELU) v = fmaxf(v, 0.f);
+                    const int po = p0 + i;
+                    if (full && (HEAD || interior)) {
+                        if (HEAD) head[po * 4 + n] = v;
+                        else out[po * PO + n] = f2bf(v);
+                    } else if (po < M) {
+                        if (HEAD) {
+                            head[po * 4 + n] = v;
+                        } else {
+                            const int gy = oy0 + po / NO, gx = ox0 + po % NO;
+                            const bool inside = gy >= 0 && gy < Ho && gx >= 0 && gx < Wo;
+                            out[po * PO + n] = inside ? f2bf(v) : (uint16_t)0;
+                        }
                     }
                 }
             }
@@ -484,41 +512,50 @@ __device__ __forceinline__ void conv_tile(const uint16_t* in, uint16_t* out, flo
     }
 }
 
-// The input tile (4x4 box means of cur and ref, as k_downdiff; 0 outside):
-// each work item is one row of 4 adjacent input pixels, whose 32 frame
-// words are all requested before any is used.
+// The input tile (4x4 box means of cur and ref, as k_downdiff; 0 outside).
+// A work item is 4 adjacent input pixels of one row: 16 bytes of each of 4
+// source rows in each frame.  The tile origin and the input grid's width are
+// multiples of 4 pixels, so the 4 pixels are all inside the frame or all
+// outside; outside items read a clamped in-frame address and use zeros, so
+// every load of an item is issued before any is used.  Rows are 4-byte
+// aligned, which is all a 16-byte global load needs.
 __device__ __forceinline__ void input_tile(uint16_t* rc, const uint8_t* cp, const uint8_t* rp, int pitch, int y0,
                                            int x0, int H4, int W4) {
-    constexpr int G = (kN0 + 3) / 4;  // groups of 4 pixels per row
+    constexpr int G = (kN0 + 3) / 4;  // items per row; the last one holds kN0 - 4 (G - 1) tile pixels
     for (int it = threadIdx.x; it < kN0 * G; it += blockDim.x) {
-        const int i = it / G, q = it % G;
-        const int gy = y0 + i;
-        const bool yin = gy >= 0 && gy < H4;
-        uint32_t c[4][4], r[4][4];
+        const int i = it / G, q = it - (it / G) * G;
+        const int gy = y0 + i, gx = x0 + 4 * q;
+        const bool in = gy >= 0 && gy < H4 && gx >= 0 && gx < W4;
+        const int cy = min(max(gy, 0), H4 - 1), cx = min(max(gx, 0), W4 - 4);
+        const size_t off = (size_t)(4 * cy) * pitch + 4 * cx;
+        uint4 c[4], r[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int gx = x0 + 4 * q + u;
-            const bool in = yin && gx >= 0 && gx < W4 && 4 * q + u < kN0;
+        for (int j = 0; j < 4; ++j) {
+            const size_t o = off + (size_t)j * pitch;
+            const uint32_t* cw = reinterpret_cast<const uint32_t*>(cp + o);
+            const uint32_t* rw = reinterpret_cast<const uint32_t*>(rp + o);
+            c[j] = make_uint4(cw[0], cw[1], cw[2], cw[3]);
+            r[j] = make_uint4(rw[0], rw[1], rw[2], rw[3]);
+        }
+        uint32_t sc[4] = {0u, 0u, 0u, 0u}, sr[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                c[u][j] = in ? *reinterpret_cast<const uint32_t*>(cp + (size_t)(4 * gy + j) * pitch + 4 * gx) : 0u;
-                r[u][j] = in ? *reinterpret_cast<const uint32_t*>(rp + (size_t)(4 * gy + j) * pitch + 4 * gx) : 0u;
-            }
+        for (int j = 0; j < 4; ++j) {
+            sc[0] = __builtin_amdgcn_sad_u8(c[j].x, 0u, sc[0]);
+            sc[1] = __builtin_amdgcn_sad_u8(c[j].y, 0u, sc[1]);
+            sc[2] = __builtin_amdgcn_sad_u8(c[j].z, 0u, sc[2]);
+            sc[3] = __builtin_amdgcn_sad_u8(c[j].w, 0u, sc[3]);
+            sr[0] = __builtin_amdgcn_sad_u8(r[j].x, 0u, sr[0]);
+            sr[1] = __builtin_amdgcn_sad_u8(r[j].y, 0u, sr[1]);
+            sr[2] = __builtin_amdgcn_sad_u8(r[j].z, 0u, sr[2]);
+            sr[3] = __builtin_amdgcn_sad_u8(r[j].w, 0u, sr[3]);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int jx = 4 * q + u;
             if (jx >= kN0) continue;
-            const int gx = x0 + jx;
             uint2 o = make_uint2(0u, 0u);
-            if (yin && gx >= 0 && gx < W4) {
-                uint32_t sc = 0, sr = 0;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    sc = __builtin_amdgcn_sad_u8(c[u][j], 0u, sc);
-                    sr = __builtin_amdgcn_sad_u8(r[u][j], 0u, sr);
-                }
-                const float mc = (float)sc * (1.0f / 16.0f), mr = (float)sr * (1.0f / 16.0f);
+            if (in) {
+                const float mc = (float)sc[u] * (1.0f / 16.0f), mr = (float)sr[u] * (1.0f / 16.0f);
                 o.x = (uint32_t)f2bf((mc - mr) * (1.0f / 32.0f)) |
                       ((uint32_t)f2bf((mc - 128.0f) * (1.0f / 64.0f)) << 16);
             }
@@ -560,7 +597,18 @@ __global__ __launch_bounds__(kFusedThreads) void k_proposer_infer(
     const int H4 = 4 * Hb, W4 = 4 * Wb, H8 = 2 * Hb, W8 = 2 * Wb;
     const int tx = (Wb + kTB - 1) / kTB, ty = (Hb + kTB - 1) / kTB;
     const int total = tx * ty * n_pairs;
-    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    // Tile order: blocks are dealt to the 8 XCDs round-robin, so when the
+    // grid is a multiple of 8 the workgroups of one XCD take one contiguous
+    // eighth of the tiles, side by side, and a tile's halo has mostly been
+    // read through the same L2 by its neighbour.
+    int first = blockIdx.x, step = gridDim.x, end = total;
+    if (gridDim.x % 8 == 0) {
+        const int x = blockIdx.x % 8;
+        first = (int)((long long)total * x / 8) + blockIdx.x / 8;
+        end = (int)((long long)total * (x + 1) / 8);
+        step = gridDim.x / 8;
+    }
+    for (int t = first; t < end; t += step) {
         const int p = t / (tx * ty), r = t % (tx * ty);
         const int bx0 = (r % tx) * kTB, by0 = (r / tx) * kTB;
         // Tile origins per layer (grid coordinates of local (0, 0)).
@@ -571,14 +619,14 @@ __global__ __launch_bounds__(kFusedThreads) void k_proposer_infer(
         input_tile(rc, cur + (long long)p * pair_stride, ref + (long long)p * pair_stride, pitch, y1 - 1, x1 - 1, H4,
                    W4);
         __syncthreads();
-        conv_tile<4, 16, 1, kN0, kN1, kP0, kP1, true, false>(rc, l1, nullptr, wl, bl, y1, x1, H4, W4);
+        conv_tile<4, 16, 1, kN0, kN1, kP0, kP1, true, false, kU1>(rc, l1, nullptr, wl, bl, y1, x1, H4, W4);
         __syncthreads();
-        conv_tile<16, 32, 2, kN1, kN2, kP1, kP2, true, false>(l1, l2, nullptr, wl + kWOff1, bl + 16, y2, x2, H8, W8);
+        conv_tile<16, 32, 2, kN1, kN2, kP1, kP2, true, false, kU2>(l1, l2, nullptr, wl + kWOff1, bl + 16, y2, x2, H8, W8);
         __syncthreads();
-        conv_tile<32, 32, 2, kN2, kN3, kP2, kP3, true, false>(l2, rc, nullptr, wl + kWOff2, bl + 48, y3, x3, Hb, Wb);
+        conv_tile<32, 32, 2, kN2, kN3, kP2, kP3, true, false, kU3>(l2, rc, nullptr, wl + kWOff2, bl + 48, y3, x3, Hb, Wb);
         __syncthreads();
         // Head over the kTB x kTB blocks: local L3 (1 + i, 1 + j) is block (by0 + i, bx0 + j).
-        conv_tile<32, 4, 1, kN3, kTB, kP3, 4, false, true>(rc, nullptr, head, wl + kWOff3, bl + 80, by0, bx0, Hb, Wb);
+        conv_tile<32, 4, 1, kN3, kTB, kP3, 4, false, true, 1>(rc, nullptr, head, wl + kWOff3, bl + 80, by0, bx0, Hb, Wb);
         __syncthreads();
         if (threadIdx.x < kTB * kTB) {
             const int i = threadIdx.x / kTB, j = threadIdx.x % kTB;

@@ -140,6 +140,25 @@ def test_infer_decodes_the_head(frames):
     assert np.array_equal(o.cpu().numpy(), eo)
 
 
+@pytest.mark.parametrize("crop", [(8, 216, 4, 340), (0, 144, 0, 384), (16, 48, 32, 64)])
+def test_infer_ragged_views(frames, crop):
+    """The fused inference kernel on frames whose block grid leaves partial
+    tiles (13x21, 9x24, 2x2 blocks), read through views whose rows start
+    4-byte (not 16-byte) aligned, equals forward() + decode on a copy."""
+    y0, y1, x0, x1 = crop
+    p = me.Proposer(seed=9)
+    full = dev(frames)
+    cur, ref = full[1:, y0:y1, x0:x1], full[:-1, y0:y1, x0:x1]
+    say("crop", crop, "pitch", cur.stride(-2), "pointer mod 16", cur.data_ptr() % 16)
+    head = p.forward(cur.contiguous(), ref.contiguous()).cpu().numpy()
+    s, o = p.infer(cur, ref, 15)
+    es = np.clip(np.rint(head[..., :2].astype(np.float32) * np.float32(8)), -15, 15).astype(np.int16)
+    eo = (head[..., 2] > 0).astype(np.uint8)
+    assert s.shape == (2, (y1 - y0) // 16, (x1 - x0) // 16, 2)
+    assert np.array_equal(s.cpu().numpy(), es)
+    assert np.array_equal(o.cpu().numpy(), eo)
+
+
 def test_dcds_learned_equals_seeded_dcds(frames):
     p = me.Proposer(seed=8)
     cur, ref = dev(frames[1:]), dev(frames[:-1])
