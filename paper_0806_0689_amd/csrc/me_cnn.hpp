@@ -38,13 +38,23 @@ __host__ __device__ constexpr int pad16(int v) { return (v + 15) / 16 * 16; }
 __device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-__device__ __forceinline__ v4s as_v4s(uint2 v) {
-    v4s r;
-    r[0] = (short)(v.x & 0xFFFFu);
-    r[1] = (short)(v.x >> 16);
-    r[2] = (short)(v.y & 0xFFFFu);
-    r[3] = (short)(v.y >> 16);
-    return r;
+__device__ __forceinline__ v4s as_v4s(uint2 v) { return __builtin_bit_cast(v4s, v); }
+
+// Two floats to a packed pair of bfloat16 (low = a), each rounded as f2bf.
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf2(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((v2f){a, b}, v2bf));
+}
+
+// LDS addressing by 32-bit byte address.
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
+}
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(3))) T* lds_ptr(uint32_t a) {
+    return (__attribute__((address_space(3))) T*)(uintptr_t)a;
 }
 
 // ---------------------------------------------------------------------------
@@ -112,24 +122,25 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ i
             const int n = t * 16 + m;
             uint2 bv = make_uint2(0u, 0u);
             if (n < COUT) bv = *reinterpret_cast<const uint2*>(Wf + (long long)n * KP + k);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, as_v4s(bv), acc[t], 0, 0, 0);
+            // Weights as the row operand: lane (m, kq) receives channels
+            // 16 t + 4 kq .. + 3 of pixel ox.
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(as_v4s(bv), a, acc[t], 0, 0, 0);
         }
     }
+    if (ox >= Wo) return;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-        const int n = t * 16 + m;
-        if (n >= COUT) continue;
-        const float bn = bias[n];
+        const int n0 = t * 16 + 4 * kq;
+        if (n0 >= COUT) continue;
+        float v[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int x = seg * 16 + 4 * kq + i;
-            if (x >= Wo) continue;
-            float v = acc[t][i] + bn;
-            if (RELU) v = fmaxf(v, 0.f);
-            const long long o = (((long long)p * Ho + oy) * Wo + x) * COUT + n;
-            if (F32OUT) reinterpret_cast<float*>(out)[o] = v;
-            else reinterpret_cast<uint16_t*>(out)[o] = f2bf(v);
+        for (int r = 0; r < 4; ++r) {
+            v[r] = acc[t][r] + bias[n0 + r];
+            if (RELU) v[r] = fmaxf(v[r], 0.f);
         }
+        const long long o = (((long long)p * Ho + oy) * Wo + ox) * COUT + n0;
+        if (F32OUT) *reinterpret_cast<float4*>(reinterpret_cast<float*>(out) + o) = make_float4(v[0], v[1], v[2], v[3]);
+        else *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(out) + o) = make_uint2(pack_bf2(v[0], v[1]), pack_bf2(v[2], v[3]));
     }
 }
 
@@ -396,30 +407,18 @@ constexpr int kWOff1 = wsize(0), kWOff2 = kWOff1 + wsize(1), kWOff3 = kWOff2 + w
 constexpr int kBias = 16 + 32 + 32 + 4;
 constexpr size_t kFusedLds =
     2 * (size_t)(kSz1 + kSz2 + kRegC + kWAll) + 4 * (size_t)(4 * kTB * kTB) + 4 * (size_t)kBias;
-#ifndef ME_PROP_THREADS
-#define ME_PROP_THREADS 1024
-#endif
-#ifndef ME_PROP_U1
-#define ME_PROP_U1 1
-#endif
-#ifndef ME_PROP_U2
-#define ME_PROP_U2 1
-#endif
-#ifndef ME_PROP_U3
-#define ME_PROP_U3 1
-#endif
-constexpr int kFusedThreads = ME_PROP_THREADS;
-// M-tiles per wave iteration in layers 1-3.
-constexpr int kU1 = ME_PROP_U1, kU2 = ME_PROP_U2, kU3 = ME_PROP_U3;
+constexpr int kFusedThreads = 1024;
 
 // One 3x3 layer from an LDS tile to an LDS tile (or, for the head, to the
 // head buffer).  NI/NO: input/output tile sides; PI/PO: pixel pitches; W:
 // this layer's weights in LDS ([COUT][KP + 4]); (oy0, ox0): output tile
 // origin in its layer's grid of Ho x Wo (outputs outside are written as 0,
-// the next layer's padding).  A lane's operand address is a per-tile base
-// plus a per-k-step offset fixed for the layer (a compile-time constant
-// beyond the lane's channel group when CIN >= 16).
-template <int CIN, int COUT, int S, int NI, int NO, int PI, int PO, bool RELU, bool HEAD, int U>
+// the next layer's padding).  The weights are the MFMA row operand and 16
+// output pixels the column operand, so lane (m, kq) receives channels
+// 16 t + 4 kq .. + 3 of pixel m and stores them as one 8-byte word.  A lane's
+// operand address is a per-tile base plus a per-k-step offset fixed for the
+// layer.
+template <int CIN, int COUT, int S, int NI, int NO, int PI, int PO, bool RELU, bool HEAD>
 __device__ __forceinline__ void conv_tile(const uint16_t* in, uint16_t* out, float* head, const uint16_t* W,
                                           const float* bias, int oy0, int ox0, int Ho, int Wo) {
     constexpr int KP = pad16(9 * CIN);
@@ -428,85 +427,75 @@ __device__ __forceinline__ void conv_tile(const uint16_t* in, uint16_t* out, flo
     constexpr int M = NO * NO;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int m = lane & 15, kq = lane >> 4;
-    v4s b[KS][NT];
-    int aoff[KS];
+    v4s w[KS][NT];
+    // Operand byte offset of k-step ks: with CIN >= 16 a k-step stays within
+    // one tap, so it is a constant plus the lane's channel group.
+    uint32_t aoff[CIN >= 16 ? 1 : KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-        int tap, ci;
-        if constexpr (CIN >= 16) {
-            tap = 16 * ks / CIN;
-            ci = 16 * ks % CIN + 4 * kq;
-        } else {
-            tap = (16 * ks + 4 * kq) / CIN;
-            ci = (16 * ks + 4 * kq) % CIN;
+        if constexpr (CIN < 16) {
+            const int tap = (16 * ks + 4 * kq) / CIN, ci = (16 * ks + 4 * kq) % CIN;
+            // Padded reduction indices (tap >= 9) read the pixel itself:
+            // finite data against zero weights, which adds exact zeros.
+            aoff[ks] = 2u * (uint32_t)(tap < 9 ? ((tap / 3) * NI + tap % 3) * PI + ci : ci);
         }
-        // Padded reduction indices (tap >= 9, layer 1 only) read the pixel
-        // itself: finite data against zero weights, which adds exact zeros.
-        aoff[ks] = tap < 9 ? ((tap / 3) * NI + tap % 3) * PI + ci : ci;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             const int n = t * 16 + m;
             uint2 bv = make_uint2(0u, 0u);
             if (n < COUT) bv = *reinterpret_cast<const uint2*>(W + n * (KP + 4) + ks * 16 + 4 * kq);
-            b[ks][t] = as_v4s(bv);
+            w[ks][t] = as_v4s(bv);
         }
     }
-    float bn[NT];
+    float bn[NT][4];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) bn[t] = t * 16 + m < COUT ? bias[t * 16 + m] : 0.f;
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) bn[t][r] = t * 16 + 4 * kq + r < COUT ? bias[t * 16 + 4 * kq + r] : 0.f;
     const bool interior = oy0 >= 0 && ox0 >= 0 && oy0 + NO <= Ho && ox0 + NO <= Wo;
-    // Each wave takes U M-tiles at a time: their MFMA chains are independent,
-    // so the operand reads of one overlap the products of the others.
-    for (int tile0 = wave * U; tile0 * 16 < M; tile0 += nw * U) {
-        // A lane's A row (output pixel); rows past the tile, and tiles past
-        // the layer, read the last pixel and are never stored.
-        const uint16_t* ab[U];
-        v4f acc[U][NT];
+    const uint32_t ib = lds_addr(in), ob = HEAD ? lds_addr(head) : lds_addr(out);
+    for (int tile = wave; tile * 16 < M; tile += nw) {
+        // This lane's output pixel; past the layer it reads the last pixel
+        // and stores nothing.
+        const int po = tile * 16 + m;
+        const int pa = min(po, M - 1);
+        const int ay = pa / NO, ax = pa - ay * NO;
+        const uint32_t ab = ib + 2u * (uint32_t)((S * ay * NI + S * ax) * PI) + (CIN >= 16 ? 8u * kq : 0u);
+        v4f acc[NT];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int pa = min((tile0 + u) * 16 + m, M - 1);
-            const int ay = pa / NO, ax = pa - ay * NO;
-            ab[u] = in + (S * ay * NI + S * ax) * PI;
-#pragma unroll
-            for (int t = 0; t < NT; ++t) acc[u][t] = v4f{0.f, 0.f, 0.f, 0.f};
-        }
+        for (int t = 0; t < NT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            v4s a[U];
+            uint32_t off;
+            if constexpr (CIN >= 16) {
+                const int tap = 16 * ks / CIN;
+                off = 2u * (uint32_t)(((tap / 3) * NI + tap % 3) * PI + 16 * ks % CIN);
+            } else {
+                off = aoff[ks];
+            }
+            const v4s a = *lds_ptr<const v4s>(ab + off);
 #pragma unroll
-            for (int u = 0; u < U; ++u) a[u] = as_v4s(*reinterpret_cast<const uint2*>(ab[u] + aoff[ks]));
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-#pragma unroll
-                for (int t = 0; t < NT; ++t)
-                    acc[u][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[u], b[ks][t], acc[u][t], 0, 0, 0);
+            for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w[ks][t], a, acc[t], 0, 0, 0);
         }
+        if (po >= M) continue;
+        const bool inside =
+            HEAD || interior || (oy0 + ay >= 0 && oy0 + ay < Ho && ox0 + ax >= 0 && ox0 + ax < Wo);
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int p0 = (tile0 + u) * 16 + 4 * kq;
-            const bool full = (tile0 + u) * 16 + 16 <= M;  // uniform: every row of this tile is an output
+        for (int t = 0; t < NT; ++t) {
+            const int n0 = t * 16 + 4 * kq;
+            if (n0 >= COUT) continue;
+            float v[4];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const int n = t * 16 + m;
-                if (n >= COUT) continue;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    float v = acc[u][t][i] + bn[t];
-                    if (RELU) v = fmaxf(v, 0.f);
-                    const int po = p0 + i;
-                    if (full && (HEAD || interior)) {
-                        if (HEAD) head[po * 4 + n] = v;
-                        else out[po * PO + n] = f2bf(v);
-                    } else if (po < M) {
-                        if (HEAD) {
-                            head[po * 4 + n] = v;
-                        } else {
-                            const int gy = oy0 + po / NO, gx = ox0 + po % NO;
-                            const bool inside = gy >= 0 && gy < Ho && gx >= 0 && gx < Wo;
-                            out[po * PO + n] = inside ? f2bf(v) : (uint16_t)0;
-                        }
-                    }
-                }
+            for (int r = 0; r < 4; ++r) {
+                v[r] = acc[t][r] + bn[t][r];
+                if (RELU) v[r] = fmaxf(v[r], 0.f);
+            }
+            if (HEAD) {
+                *lds_ptr<v4f>(ob + 4u * (uint32_t)(po * 4 + n0)) = v4f{v[0], v[1], v[2], v[3]};
+            } else {
+                v2u o = v2u{pack_bf2(v[0], v[1]), pack_bf2(v[2], v[3])};
+                if (!inside) o = v2u{0u, 0u};
+                *lds_ptr<v2u>(ob + 2u * (uint32_t)(po * PO + n0)) = o;
             }
         }
     }
@@ -619,14 +608,14 @@ __global__ __launch_bounds__(kFusedThreads) void k_proposer_infer(
         input_tile(rc, cur + (long long)p * pair_stride, ref + (long long)p * pair_stride, pitch, y1 - 1, x1 - 1, H4,
                    W4);
         __syncthreads();
-        conv_tile<4, 16, 1, kN0, kN1, kP0, kP1, true, false, kU1>(rc, l1, nullptr, wl, bl, y1, x1, H4, W4);
+        conv_tile<4, 16, 1, kN0, kN1, kP0, kP1, true, false>(rc, l1, nullptr, wl, bl, y1, x1, H4, W4);
         __syncthreads();
-        conv_tile<16, 32, 2, kN1, kN2, kP1, kP2, true, false, kU2>(l1, l2, nullptr, wl + kWOff1, bl + 16, y2, x2, H8, W8);
+        conv_tile<16, 32, 2, kN1, kN2, kP1, kP2, true, false>(l1, l2, nullptr, wl + kWOff1, bl + 16, y2, x2, H8, W8);
         __syncthreads();
-        conv_tile<32, 32, 2, kN2, kN3, kP2, kP3, true, false, kU3>(l2, rc, nullptr, wl + kWOff2, bl + 48, y3, x3, Hb, Wb);
+        conv_tile<32, 32, 2, kN2, kN3, kP2, kP3, true, false>(l2, rc, nullptr, wl + kWOff2, bl + 48, y3, x3, Hb, Wb);
         __syncthreads();
         // Head over the kTB x kTB blocks: local L3 (1 + i, 1 + j) is block (by0 + i, bx0 + j).
-        conv_tile<32, 4, 1, kN3, kTB, kP3, 4, false, true, 1>(rc, nullptr, head, wl + kWOff3, bl + 80, by0, bx0, Hb, Wb);
+        conv_tile<32, 4, 1, kN3, kTB, kP3, 4, false, true>(rc, nullptr, head, wl + kWOff3, bl + 80, by0, bx0, Hb, Wb);
         __syncthreads();
         if (threadIdx.x < kTB * kTB) {
             const int i = threadIdx.x / kTB, j = threadIdx.x % kTB;
