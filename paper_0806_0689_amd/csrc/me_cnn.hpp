@@ -399,14 +399,15 @@ constexpr int kTB = 8;
 constexpr int kN3 = kTB + 2, kN2 = 2 * kN3 + 1, kN1 = 2 * kN2 + 1, kN0 = kN1 + 2;
 constexpr int kP0 = 4, kP1 = 20, kP2 = 40, kP3 = 40;  // pixel pitches
 constexpr int kSz0 = kN0 * kN0 * kP0, kSz1 = kN1 * kN1 * kP1, kSz2 = kN2 * kN2 * kP2, kSz3 = kN3 * kN3 * kP3;
-constexpr int kRegC = kSz0 > kSz3 ? kSz0 : kSz3;
 // Weights in LDS: layer l as [COUT][KP + 4] bf16.
 __host__ __device__ constexpr int wrow(int l) { return pad16(9 * kLayers[l].cin) + 4; }
 __host__ __device__ constexpr int wsize(int l) { return kLayers[l].cout * wrow(l); }
 constexpr int kWOff1 = wsize(0), kWOff2 = kWOff1 + wsize(1), kWOff3 = kWOff2 + wsize(2), kWAll = kWOff3 + wsize(3);
 constexpr int kBias = 16 + 32 + 32 + 4;
-constexpr size_t kFusedLds =
-    2 * (size_t)(kSz1 + kSz2 + kRegC + kWAll) + 4 * (size_t)(4 * kTB * kTB) + 4 * (size_t)kBias;
+// LDS: l1, l2 (also the input tile), l3, the weights, then the fp32 head
+// (16-byte aligned for its 4-channel stores) and the biases.
+constexpr size_t kHeadByte = (2 * (size_t)(kSz1 + kSz2 + kSz3 + kWAll) + 15) / 16 * 16;
+constexpr size_t kFusedLds = kHeadByte + 4 * (size_t)(4 * kTB * kTB + kBias);
 constexpr int kFusedThreads = 1024;
 
 // One 3x3 layer from an LDS tile to an LDS tile (or, for the head, to the
@@ -425,7 +426,9 @@ __device__ __forceinline__ void conv_tile(const uint16_t* in, uint16_t* out, flo
     constexpr int KS = KP / 16;
     constexpr int NT = (COUT + 15) / 16;
     constexpr int M = NO * NO;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wave * 16 >= M) return;  // no output tile for this wave: skip the weight reads
     const int m = lane & 15, kq = lane >> 4;
     v4s w[KS][NT];
     // Operand byte offset of k-step ks: with CIN >= 16 a k-step stays within
@@ -508,53 +511,66 @@ __device__ __forceinline__ void conv_tile(const uint16_t* in, uint16_t* out, flo
 // outside; outside items read a clamped in-frame address and use zeros, so
 // every load of an item is issued before any is used.  Rows are 4-byte
 // aligned, which is all a 16-byte global load needs.
-__device__ __forceinline__ void input_tile(uint16_t* rc, const uint8_t* cp, const uint8_t* rp, int pitch, int y0,
-                                           int x0, int H4, int W4) {
-    constexpr int G = (kN0 + 3) / 4;  // items per row; the last one holds kN0 - 4 (G - 1) tile pixels
-    for (int it = threadIdx.x; it < kN0 * G; it += blockDim.x) {
-        const int i = it / G, q = it - (it / G) * G;
-        const int gy = y0 + i, gx = x0 + 4 * q;
-        const bool in = gy >= 0 && gy < H4 && gx >= 0 && gx < W4;
-        const int cy = min(max(gy, 0), H4 - 1), cx = min(max(gx, 0), W4 - 4);
-        const size_t off = (size_t)(4 * cy) * pitch + 4 * cx;
-        uint4 c[4], r[4];
+constexpr int kInG = (kN0 + 3) / 4;  // items per row; the last holds kN0 - 4 (kInG - 1) tile pixels
+constexpr int kInItems = kN0 * kInG;
+
+__device__ __forceinline__ void input_item(int it, const uint8_t* cp, const uint8_t* rp, int pitch, int y0, int x0,
+                                           int H4, int W4, uint2 (&o)[4]) {
+    const int i = it / kInG, q = it - (it / kInG) * kInG;
+    const int gy = y0 + i, gx = x0 + 4 * q;
+    const bool in = gy >= 0 && gy < H4 && gx >= 0 && gx < W4;
+    const int cy = min(max(gy, 0), H4 - 1), cx = min(max(gx, 0), W4 - 4);
+    const size_t off = (size_t)(4 * cy) * pitch + 4 * cx;
+    uint4 c[4], r[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const size_t o = off + (size_t)j * pitch;
-            const uint32_t* cw = reinterpret_cast<const uint32_t*>(cp + o);
-            const uint32_t* rw = reinterpret_cast<const uint32_t*>(rp + o);
-            c[j] = make_uint4(cw[0], cw[1], cw[2], cw[3]);
-            r[j] = make_uint4(rw[0], rw[1], rw[2], rw[3]);
-        }
-        uint32_t sc[4] = {0u, 0u, 0u, 0u}, sr[4] = {0u, 0u, 0u, 0u};
+    for (int j = 0; j < 4; ++j) {
+        const size_t a = off + (size_t)j * pitch;
+        const uint32_t* cw = reinterpret_cast<const uint32_t*>(cp + a);
+        const uint32_t* rw = reinterpret_cast<const uint32_t*>(rp + a);
+        c[j] = make_uint4(cw[0], cw[1], cw[2], cw[3]);
+        r[j] = make_uint4(rw[0], rw[1], rw[2], rw[3]);
+    }
+    uint32_t sc[4] = {0u, 0u, 0u, 0u}, sr[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            sc[0] = __builtin_amdgcn_sad_u8(c[j].x, 0u, sc[0]);
-            sc[1] = __builtin_amdgcn_sad_u8(c[j].y, 0u, sc[1]);
-            sc[2] = __builtin_amdgcn_sad_u8(c[j].z, 0u, sc[2]);
-            sc[3] = __builtin_amdgcn_sad_u8(c[j].w, 0u, sc[3]);
-            sr[0] = __builtin_amdgcn_sad_u8(r[j].x, 0u, sr[0]);
-            sr[1] = __builtin_amdgcn_sad_u8(r[j].y, 0u, sr[1]);
-            sr[2] = __builtin_amdgcn_sad_u8(r[j].z, 0u, sr[2]);
-            sr[3] = __builtin_amdgcn_sad_u8(r[j].w, 0u, sr[3]);
-        }
+    for (int j = 0; j < 4; ++j) {
+        sc[0] = __builtin_amdgcn_sad_u8(c[j].x, 0u, sc[0]);
+        sc[1] = __builtin_amdgcn_sad_u8(c[j].y, 0u, sc[1]);
+        sc[2] = __builtin_amdgcn_sad_u8(c[j].z, 0u, sc[2]);
+        sc[3] = __builtin_amdgcn_sad_u8(c[j].w, 0u, sc[3]);
+        sr[0] = __builtin_amdgcn_sad_u8(r[j].x, 0u, sr[0]);
+        sr[1] = __builtin_amdgcn_sad_u8(r[j].y, 0u, sr[1]);
+        sr[2] = __builtin_amdgcn_sad_u8(r[j].z, 0u, sr[2]);
+        sr[3] = __builtin_amdgcn_sad_u8(r[j].w, 0u, sr[3]);
+    }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int jx = 4 * q + u;
-            if (jx >= kN0) continue;
-            uint2 o = make_uint2(0u, 0u);
-            if (in) {
-                const float mc = (float)sc[u] * (1.0f / 16.0f), mr = (float)sr[u] * (1.0f / 16.0f);
-                o.x = (uint32_t)f2bf((mc - mr) * (1.0f / 32.0f)) |
-                      ((uint32_t)f2bf((mc - 128.0f) * (1.0f / 64.0f)) << 16);
-            }
-            *reinterpret_cast<uint2*>(rc + (i * kN0 + jx) * kP0) = o;
-        }
+    for (int u = 0; u < 4; ++u) {
+        const float mc = (float)sc[u] * (1.0f / 16.0f), mr = (float)sr[u] * (1.0f / 16.0f);
+        o[u] = in ? make_uint2((uint32_t)f2bf((mc - mr) * (1.0f / 32.0f)) |
+                                   ((uint32_t)f2bf((mc - 128.0f) * (1.0f / 64.0f)) << 16),
+                               0u)
+                  : make_uint2(0u, 0u);
     }
 }
 
+__device__ __forceinline__ void input_store(uint16_t* x, int it, const uint2 (&o)[4]) {
+    const int i = it / kInG, q = it - (it / kInG) * kInG;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (4 * q + u < kN0) *reinterpret_cast<uint2*>(x + (i * kN0 + 4 * q + u) * kP0) = o[u];
+}
+
+// Layer 3's M-tiles take waves [0, kW3); the rest load the next tile's input
+// meanwhile.
+constexpr int kW3 = (kN3 * kN3 + 15) / 16;
+static_assert((kFusedThreads / 64 - kW3) * 64 >= kInItems, "input prefetch needs one item per idle lane");
+static_assert(kSz0 <= kSz2, "the input tile lives in layer 2's buffer");
+
 // grid: min(tiles, CUs) workgroups of kFusedThreads threads, kFusedLds bytes.
 // wf/bias: the packed layer weights ([COUT][KP]) and biases.
+//
+// Per tile: L1 (input -> l1), L2 (l1 -> l2), then L3 (l2 -> l3) while the
+// idle waves fetch and reduce the next tile's input, then the head (l3 ->
+// head) while they store it into l2's buffer, whose last reader was L3.
 __global__ __launch_bounds__(kFusedThreads) void k_proposer_infer(
     const uint8_t* __restrict__ cur, const uint8_t* __restrict__ ref, int pitch, long long pair_stride, int Hb, int Wb,
     int n_pairs, const uint16_t* __restrict__ wf0, const uint16_t* __restrict__ wf1,
@@ -563,11 +579,12 @@ __global__ __launch_bounds__(kFusedThreads) void k_proposer_infer(
     int16_t* __restrict__ start, uint8_t* __restrict__ orient) {
     extern __shared__ uint16_t lds[];
     uint16_t* l1 = lds;
-    uint16_t* l2 = l1 + kSz1;
-    uint16_t* rc = l2 + kSz2;  // input tile, then the L3 tile
-    uint16_t* wl = rc + kRegC;
-    float* head = reinterpret_cast<float*>(wl + kWAll);
+    uint16_t* l2 = l1 + kSz1;  // the input tile, then layer 2
+    uint16_t* l3 = l2 + kSz2;
+    uint16_t* wl = l3 + kSz3;
+    float* head = reinterpret_cast<float*>(reinterpret_cast<char*>(lds) + kHeadByte);
     float* bl = head + 4 * kTB * kTB;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     // Weights and biases, once.
     {
         const uint16_t* src[4] = {wf0, wf1, wf2, wf3};
@@ -597,25 +614,51 @@ __global__ __launch_bounds__(kFusedThreads) void k_proposer_infer(
         end = (int)((long long)total * (x + 1) / 8);
         step = gridDim.x / 8;
     }
+    // Tile t: its pair and first block.  Its input tile starts 8 input
+    // pixels (the halo of three 3x3 layers, two of stride 2) before the
+    // first block's 4 input pixels per block, at (4 by0 - 8, 4 bx0 - 8).
+    auto place = [&](int t, int& p, int& by0, int& bx0) {
+        p = t / (tx * ty);
+        const int r = t - p * (tx * ty);
+        bx0 = (r % tx) * kTB;
+        by0 = (r / tx) * kTB;
+    };
+    if (first < end) {
+        int p, by0, bx0;
+        place(first, p, by0, bx0);
+        for (int it = threadIdx.x; it < kInItems; it += blockDim.x) {
+            uint2 o[4];
+            input_item(it, cur + (long long)p * pair_stride, ref + (long long)p * pair_stride, pitch, 4 * by0 - 8,
+                       4 * bx0 - 8, H4, W4, o);
+            input_store(l2, it, o);
+        }
+    }
+    __syncthreads();
     for (int t = first; t < end; t += step) {
-        const int p = t / (tx * ty), r = t % (tx * ty);
-        const int bx0 = (r % tx) * kTB, by0 = (r / tx) * kTB;
+        int p, by0, bx0;
+        place(t, p, by0, bx0);
         // Tile origins per layer (grid coordinates of local (0, 0)).
         const int y3 = by0 - 1, x3 = bx0 - 1;
         const int y2 = 2 * y3 - 1, x2 = 2 * x3 - 1;
         const int y1 = 2 * y2 - 1, x1 = 2 * x2 - 1;
-        __syncthreads();  // the previous tile's readers of every buffer are done
-        input_tile(rc, cur + (long long)p * pair_stride, ref + (long long)p * pair_stride, pitch, y1 - 1, x1 - 1, H4,
-                   W4);
-        __syncthreads();
-        conv_tile<4, 16, 1, kN0, kN1, kP0, kP1, true, false>(rc, l1, nullptr, wl, bl, y1, x1, H4, W4);
+        conv_tile<4, 16, 1, kN0, kN1, kP0, kP1, true, false>(l2, l1, nullptr, wl, bl, y1, x1, H4, W4);
         __syncthreads();
         conv_tile<16, 32, 2, kN1, kN2, kP1, kP2, true, false>(l1, l2, nullptr, wl + kWOff1, bl + 16, y2, x2, H8, W8);
         __syncthreads();
-        conv_tile<32, 32, 2, kN2, kN3, kP2, kP3, true, false>(l2, rc, nullptr, wl + kWOff2, bl + 48, y3, x3, Hb, Wb);
+        conv_tile<32, 32, 2, kN2, kN3, kP2, kP3, true, false>(l2, l3, nullptr, wl + kWOff2, bl + 48, y3, x3, Hb, Wb);
+        const int it = (int)threadIdx.x - 64 * kW3;
+        const bool fetch = wave >= kW3 && t + step < end && it < kInItems;
+        uint2 o[4];
+        if (fetch) {
+            int pn, byn, bxn;
+            place(t + step, pn, byn, bxn);
+            input_item(it, cur + (long long)pn * pair_stride, ref + (long long)pn * pair_stride, pitch, 4 * byn - 8,
+                       4 * bxn - 8, H4, W4, o);
+        }
         __syncthreads();
         // Head over the kTB x kTB blocks: local L3 (1 + i, 1 + j) is block (by0 + i, bx0 + j).
-        conv_tile<32, 4, 1, kN3, kTB, kP3, 4, false, true>(rc, nullptr, head, wl + kWOff3, bl + 80, by0, bx0, Hb, Wb);
+        conv_tile<32, 4, 1, kN3, kTB, kP3, 4, false, true>(l3, nullptr, head, wl + kWOff3, bl + 80, by0, bx0, Hb, Wb);
+        if (fetch) input_store(l2, it, o);
         __syncthreads();
         if (threadIdx.x < kTB * kTB) {
             const int i = threadIdx.x / kTB, j = threadIdx.x % kTB;
