@@ -426,11 +426,20 @@ __device__ __forceinline__ void conv_tile(const uint16_t* in, uint16_t* out, flo
     constexpr int KS = KP / 16;
     constexpr int NT = (COUT + 15) / 16;
     constexpr int M = NO * NO;
+    // Weights stay in registers across a wave's M-tiles when it has more
+    // than one; otherwise each k-step reads its own.
+    constexpr bool kCache = M > 16 * (kFusedThreads / 64);
     const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (wave * 16 >= M) return;  // no output tile for this wave: skip the weight reads
     const int m = lane & 15, kq = lane >> 4;
-    v4s w[KS][NT];
+    auto weights = [&](int ks, int t) {
+        const int n = t * 16 + m;
+        uint2 bv = make_uint2(0u, 0u);
+        if (n < COUT) bv = *reinterpret_cast<const uint2*>(W + n * (KP + 4) + ks * 16 + 4 * kq);
+        return as_v4s(bv);
+    };
+    v4s w[kCache ? KS : 1][NT];
     // Operand byte offset of k-step ks: with CIN >= 16 a k-step stays within
     // one tap, so it is a constant plus the lane's channel group.
     uint32_t aoff[CIN >= 16 ? 1 : KS];
@@ -442,13 +451,9 @@ __device__ __forceinline__ void conv_tile(const uint16_t* in, uint16_t* out, flo
             // finite data against zero weights, which adds exact zeros.
             aoff[ks] = 2u * (uint32_t)(tap < 9 ? ((tap / 3) * NI + tap % 3) * PI + ci : ci);
         }
+        if constexpr (kCache)
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const int n = t * 16 + m;
-            uint2 bv = make_uint2(0u, 0u);
-            if (n < COUT) bv = *reinterpret_cast<const uint2*>(W + n * (KP + 4) + ks * 16 + 4 * kq);
-            w[ks][t] = as_v4s(bv);
-        }
+            for (int t = 0; t < NT; ++t) w[ks][t] = weights(ks, t);
     }
     float bn[NT][4];
 #pragma unroll
@@ -478,7 +483,9 @@ __device__ __forceinline__ void conv_tile(const uint16_t* in, uint16_t* out, flo
             }
             const v4s a = *lds_ptr<const v4s>(ab + off);
 #pragma unroll
-            for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w[ks][t], a, acc[t], 0, 0, 0);
+            for (int t = 0; t < NT; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(kCache ? w[kCache ? ks : 0][t] : weights(ks, t), a,
+                                                                  acc[t], 0, 0, 0);
         }
         if (po >= M) continue;
         const bool inside =
@@ -511,6 +518,8 @@ __device__ __forceinline__ void conv_tile(const uint16_t* in, uint16_t* out, flo
 // outside; outside items read a clamped in-frame address and use zeros, so
 // every load of an item is issued before any is used.  Rows are 4-byte
 // aligned, which is all a 16-byte global load needs.
+// 16 bytes at a 4-byte aligned address (one dwordx4 load).
+typedef uint32_t u32x4a4 __attribute__((ext_vector_type(4), aligned(4)));
 constexpr int kInG = (kN0 + 3) / 4;  // items per row; the last holds kN0 - 4 (kInG - 1) tile pixels
 constexpr int kInItems = kN0 * kInG;
 
@@ -521,14 +530,12 @@ __device__ __forceinline__ void input_item(int it, const uint8_t* cp, const uint
     const bool in = gy >= 0 && gy < H4 && gx >= 0 && gx < W4;
     const int cy = min(max(gy, 0), H4 - 1), cx = min(max(gx, 0), W4 - 4);
     const size_t off = (size_t)(4 * cy) * pitch + 4 * cx;
-    uint4 c[4], r[4];
+    u32x4a4 c[4], r[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const size_t a = off + (size_t)j * pitch;
-        const uint32_t* cw = reinterpret_cast<const uint32_t*>(cp + a);
-        const uint32_t* rw = reinterpret_cast<const uint32_t*>(rp + a);
-        c[j] = make_uint4(cw[0], cw[1], cw[2], cw[3]);
-        r[j] = make_uint4(rw[0], rw[1], rw[2], rw[3]);
+        c[j] = *reinterpret_cast<const u32x4a4*>(cp + a);
+        r[j] = *reinterpret_cast<const u32x4a4*>(rp + a);
     }
     uint32_t sc[4] = {0u, 0u, 0u, 0u}, sr[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
