@@ -159,6 +159,24 @@ def test_infer_ragged_views(frames, crop):
     assert np.array_equal(o.cpu().numpy(), eo)
 
 
+@pytest.mark.parametrize("shape", [(5, 256, 512), (4, 1088, 1920)])
+def test_infer_tile_order(shape):
+    """Grids that are multiples of 8 workgroups take the XCD-local tile
+    order (32 tiles on 32 workgroups; 405 tiles on at most 256): every block
+    still gets exactly forward() + decode."""
+    P, H, W = shape
+    seq = make_config(3, seed=21, frames=P)[:, :H, :W]
+    p = me.Proposer(seed=11)
+    cur, ref = dev(seq[1:]), dev(seq[:-1])
+    head = p.forward(cur, ref).cpu().numpy()
+    s, o = p.infer(cur, ref, 31)
+    es = np.clip(np.rint(head[..., :2].astype(np.float32) * np.float32(8)), -31, 31).astype(np.int16)
+    eo = (head[..., 2] > 0).astype(np.uint8)
+    say("shape", shape, "tiles", (P - 1) * ((H // 16 + 7) // 8) * ((W // 16 + 7) // 8))
+    assert np.array_equal(s.cpu().numpy(), es)
+    assert np.array_equal(o.cpu().numpy(), eo)
+
+
 def test_dcds_learned_equals_seeded_dcds(frames):
     p = me.Proposer(seed=8)
     cur, ref = dev(frames[1:]), dev(frames[:-1])
