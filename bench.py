@@ -32,6 +32,8 @@ def src_digest() -> str:
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_0806_0689_amd", "csrc")
     for fn in sorted(os.listdir(d)):
+        if not fn.startswith("me_"):  # the library's sources only
+            continue
         with open(os.path.join(d, fn), "rb") as f:
             h.update(fn.encode() + f.read())
     return h.hexdigest()[:16]
@@ -53,6 +55,19 @@ def time_launches(fn, steps, warmup, torch):
     wall = (time.perf_counter() - t0) * 1e3
     per = [s.elapsed_time(e) for s, e in zip(starts, ends)]
     return wall / steps, sum(per) / len(per), per
+
+
+def valu_rates():
+    """VALU issue rates of the SAD instructions on this device, from the
+    calibration program that build() compiles (run as a child process)."""
+    import subprocess
+    exe = os.path.join(ROOT, "paper_0806_0689_amd", "valu_rates")
+    if not os.path.exists(exe):
+        return {"status": "calibration program not built"}
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    if r.returncode != 0:
+        return {"status": "calibration program failed: %s" % r.stderr[-300:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 def traffic_for(kernel: str):
@@ -379,6 +394,19 @@ def main():
     leg("dcds", lambda: me.dcds(cur, ref, 16, RANGE), args.steps, blocks16)
     if "fs" in legs:
         leg("fs", lambda: me.fullsearch(cur, ref, 16, RANGE), max(3, min(args.steps, 10)), blocks16)
+        # FS is bound by v_qsad_pk_u16_u8 issue (16 absolute differences per
+        # lane and instruction); its peak is measured, not assumed.
+        rates = valu_rates()
+        fs = results["fs"]
+        fs["valu_roofline"] = {"bound": "alu", "instr": "v_qsad_pk_u16_u8", "rates": rates}
+        if "absdiff_per_s" in rates:
+            absd = fs["nsp_mean"] * 256 * blocks16 / (fs["ms_per_step"] * 1e-3)
+            peak = rates["absdiff_per_s"]["v_qsad_pk_u16_u8"]
+            fs["valu_roofline"].update({"achieved_absdiff_per_s": absd, "peak_absdiff_per_s": peak,
+                                        "frac": absd / peak})
+            print("# fs: %.3g absolute differences/s, %.0f%% of the measured v_qsad_pk_u16_u8 peak %.3g "
+                  "(%.1f cycles per wave instruction)" % (absd, 100 * absd / peak, peak,
+                  rates["cycles_per_wave_instruction"]["v_qsad_pk_u16_u8"]), file=sys.stderr, flush=True)
     if "dcds8" in legs:
         leg("dcds8", lambda: me.dcds(cur, ref, 8, RANGE), args.steps, blocks8)
     if "dcds_s" in legs:

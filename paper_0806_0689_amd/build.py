@@ -11,6 +11,10 @@ LIB = os.path.join(HERE, "libme.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["me_api.hip", "me_batch.hip", "me_proposer.hip"]
+# Stand-alone calibration program (VALU issue rates of the SAD instructions),
+# run by bench.py as a child process.
+RATES_SRC = "valu_rates.hip"
+RATES = os.path.join(HERE, "valu_rates")
 FLAGS = [
     "--offload-arch=gfx950",
     "-O3",
@@ -36,6 +40,9 @@ def build(verbose: bool = False) -> str:
         cmds.append([HIPCC, *[f for f in FLAGS if f != "-shared"], "-c", "-I", os.path.join(ROOT, "include"),
                      "-I", CSRC, "-o", obj, os.path.join(CSRC, src)])
     tmp = LIB + ".tmp" + tag
+    rates_tmp = RATES + ".tmp" + tag
+    cmds.append([HIPCC, *[f for f in FLAGS if f not in ("-shared", "-fPIC", "-fvisibility=hidden")], "-o", rates_tmp,
+                 os.path.join(CSRC, RATES_SRC)])
     try:
         with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
             for cmd in cmds:
@@ -48,8 +55,9 @@ def build(verbose: bool = False) -> str:
             print(" ".join(link), flush=True)
         subprocess.check_call(link)
         os.replace(tmp, LIB)
+        os.replace(rates_tmp, RATES)
     finally:
-        for o in objs + [tmp]:
+        for o in objs + [tmp, rates_tmp]:
             if os.path.exists(o):
                 os.remove(o)
     return LIB
