@@ -169,6 +169,64 @@ def test_1080p_fs_sampled_pairs(seq1080, B):
         assert_same((mv[p], sad[p], nsp[p]), exp, "1080p fs pair %d" % p)
 
 
+def crop_fs(cur, ref, B, R, bx, by):
+    """Oracle FS of one block from a crop holding its whole search window
+    (and the frame's own edges where the window meets them), so the
+    candidate set, hence the result, is the full frame's."""
+    H, W = cur.shape
+    m = (R + B - 1) // B * B  # a block-aligned margin of at least R
+    x0, y0 = max(bx * B - m, 0), max(by * B - m, 0)
+    x1, y1 = min(bx * B + B + m, W), min(by * B + B + m, H)
+    mv, sad, nsp = oracle.fullsearch(np.ascontiguousarray(cur[y0:y1, x0:x1]),
+                                     np.ascontiguousarray(ref[y0:y1, x0:x1]), B, R)
+    j, i = (by * B - y0) // B, (bx * B - x0) // B
+    return mv[j, i], sad[j, i], nsp[j, i]
+
+
+@pytest.fixture(scope="module")
+def seq4k():
+    say("generating 3 frames of the 3840x2160 sequence")
+    return make_config(5, frames=3)
+
+
+def test_4k_r31_dcds_all_blocks(seq4k):
+    """The 3840x2160, +-31 configuration: DCDS, DCDS^S and seeded DCDS over
+    two whole pairs (64 800 blocks) against the oracle."""
+    run = seq4k
+    cur, ref = run[1:], run[:-1]
+    tc, tr = to_dev(cur), to_dev(ref)
+    say("case 4k R=31 dcds")
+    assert_same(me.dcds(tc, tr, 16, 31), oracle_pairs(oracle.dcds, cur, ref, 16, 31), "4k dcds")
+    assert_same(me.dcds(tc, tr, 16, 31, algo=me.ME_ALGO_DCDS_S),
+                oracle_pairs(oracle.dcds, cur, ref, 16, 31, variant=oracle.VARIANT_DCDS_S), "4k dcds_s")
+    P, H, W = cur.shape
+    rng = np.random.default_rng(31)
+    start = rng.integers(-33, 34, (P, H // 16, W // 16, 2)).astype(np.int16)
+    orient = rng.integers(0, 2, (P, H // 16, W // 16)).astype(np.uint8)
+    got = me.dcds(tc, tr, 16, 31, start=to_dev(start), orient=to_dev(orient))
+    exp = tuple(np.stack(x) for x in zip(*[oracle.dcds(cur[p], ref[p], 16, 31, start=start[p], orient=orient[p])
+                                            for p in range(P)]))
+    assert_same(got, exp, "4k seeded")
+
+
+def test_4k_r31_fs_sampled_blocks(seq4k):
+    """FS at 3840x2160, +-31 (3969 candidates per block): the whole frame on
+    the GPU, the oracle on the four corners, edge blocks and random interior
+    blocks, each from a crop that holds its search window."""
+    cur, ref = seq4k[2], seq4k[1]
+    bh, bw = cur.shape[0] // 16, cur.shape[1] // 16
+    mv, sad, nsp = [t.cpu().numpy() for t in me.fullsearch(to_dev(cur), to_dev(ref), 16, 31)]
+    mv, sad, nsp = mv.reshape(bh, bw, 2), sad.reshape(bh, bw), nsp.reshape(bh, bw)
+    rng = np.random.default_rng(5)
+    picks = [(0, 0), (bw - 1, 0), (0, bh - 1), (bw - 1, bh - 1), (1, 1), (bw // 2, 0), (0, bh // 2), (bw - 2, bh - 2)]
+    picks += [(int(rng.integers(0, bw)), int(rng.integers(0, bh))) for _ in range(40)]
+    say("case 4k R=31 fs, %d sampled blocks" % len(picks))
+    for bx, by in picks:
+        emv, esad, ensp = crop_fs(cur, ref, 16, 31, bx, by)
+        assert (mv[by, bx] == emv).all() and sad[by, bx] == esad and nsp[by, bx] == ensp, (
+            "block", bx, by, mv[by, bx], sad[by, bx], nsp[by, bx], emv, esad, ensp)
+
+
 def ideal_cost(t, R):
     ys, xs = np.mgrid[-R:R + 1, -R:R + 1]
     return ((xs - t[0]) ** 2 + (ys - t[1]) ** 2).astype(np.int32)
