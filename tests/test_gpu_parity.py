@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
-from conftest import load_golden
+from conftest import crop_fs, load_golden
 from synth import blurred_noise, make_config, qcif_pair
 
 torch = pytest.importorskip("torch")
@@ -167,20 +167,6 @@ def test_1080p_fs_sampled_pairs(seq1080, B):
     for p in (0, 29, 58):
         exp = oracle.fullsearch(seq1080[p + 1], seq1080[p], B, 15)
         assert_same((mv[p], sad[p], nsp[p]), exp, "1080p fs pair %d" % p)
-
-
-def crop_fs(cur, ref, B, R, bx, by):
-    """Oracle FS of one block from a crop holding its whole search window
-    (and the frame's own edges where the window meets them), so the
-    candidate set, hence the result, is the full frame's."""
-    H, W = cur.shape
-    m = (R + B - 1) // B * B  # a block-aligned margin of at least R
-    x0, y0 = max(bx * B - m, 0), max(by * B - m, 0)
-    x1, y1 = min(bx * B + B + m, W), min(by * B + B + m, H)
-    mv, sad, nsp = oracle.fullsearch(np.ascontiguousarray(cur[y0:y1, x0:x1]),
-                                     np.ascontiguousarray(ref[y0:y1, x0:x1]), B, R)
-    j, i = (by * B - y0) // B, (bx * B - x0) // B
-    return mv[j, i], sad[j, i], nsp[j, i]
 
 
 @pytest.fixture(scope="module")

@@ -103,3 +103,19 @@ def test_fs_translation_recovered_exactly():
                 x, y = i * 16 + sx, j * 16 + sy
                 if 0 <= x <= 128 - 16 and 0 <= y <= 96 - 16:
                     assert tuple(mv[j, i]) == (sx, sy) and sad[j, i] == 0
+
+
+@pytest.mark.parametrize("B,R", [(16, 31), (8, 7), (16, 5)])
+def test_crop_fs_equals_whole_frame(B, R):
+    """The crop rule the 3840x2160 GPU test samples FS with: on every block
+    of a small frame (most of them edge blocks), FS on the crop equals FS on
+    the whole frame."""
+    from conftest import crop_fs
+    from synth import make_config
+    seq = make_config(5, seed=17, frames=2)[:, :160, :256]
+    cur, ref = seq[1], seq[0]
+    mv, sad, nsp = oracle.fullsearch(cur, ref, B, R)
+    for by in range(160 // B):
+        for bx in range(256 // B):
+            emv, esad, ensp = crop_fs(cur, ref, B, R, bx, by)
+            assert (mv[by, bx] == emv).all() and sad[by, bx] == esad and nsp[by, bx] == ensp, (bx, by)
