@@ -81,10 +81,9 @@ int main(void) {
 """
 
 
-@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not found")
-def test_oracle_under_asan_ubsan(tmp_path):
+def build_and_run(tmp_path, source):
     drv = tmp_path / "driver.c"
-    drv.write_text(DRIVER)
+    drv.write_text(source)
     exe = tmp_path / "driver"
     cmd = ["gcc", "-O1", "-g", "-std=c99", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
            "-fno-omit-frame-pointer", "-o", str(exe), str(drv), ORACLE]
@@ -94,7 +93,23 @@ def test_oracle_under_asan_ubsan(tmp_path):
         if "asan" in (e.stderr or "").lower() or "libubsan" in (e.stderr or "").lower():
             pytest.skip("sanitizer runtime not available: %s" % e.stderr[-200:])
         raise
-    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300,
-                       env=dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1"))
+    return subprocess.run([str(exe)], capture_output=True, text=True, timeout=300,
+                          env=dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1"))
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not found")
+def test_oracle_under_asan_ubsan(tmp_path):
+    r = build_and_run(tmp_path, DRIVER)
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
     assert "rc 0" in r.stdout
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not found")
+def test_the_instrumentation_is_live(tmp_path):
+    """A one-byte write past a frame buffer, planted in a copy of the driver,
+    must be reported: the clean run above then means something."""
+    planted = DRIVER.replace("free(cur); free(ref);", "cur[pitch * H] = 1; free(cur); free(ref);")
+    assert planted != DRIVER
+    r = build_and_run(tmp_path, planted)
+    assert r.returncode != 0
+    assert "heap-buffer-overflow" in r.stderr
