@@ -18,7 +18,8 @@
  *   - Frames are 8-bit luma, row-major, `pitch` bytes between rows, in device
  *     memory owned by the caller.  width and height must be multiples of
  *     `block`; pitch must be >= width and a multiple of 4; frame pointers must
- *     be 4-byte aligned.
+ *     be 4-byte aligned.  One frame must span less than 2 GiB (height * pitch
+ *     < 2^31; larger frames give ME_EUNSUPPORTED).
  *   - A motion vector (x, y) places the reference block at (x0 + x, y0 + y)
  *     for the current block at (x0, y0); +x right, +y down.
  *   - Candidate set of a block: |x|, |y| <= range and the displaced block wholly

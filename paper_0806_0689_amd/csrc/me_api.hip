@@ -28,6 +28,8 @@ int check_frames(const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t 
     if (range < 1 || range > 31) return ME_EUNSUPPORTED;
     if (width % block || height % block) return ME_EINVAL;
     if (pitch < width || (pitch & 3)) return ME_EINVAL;
+    // Offsets within one frame are 32-bit (and rows 24-bit products) in the kernels.
+    if ((int64_t)height * pitch > (int64_t)INT32_MAX) return ME_EUNSUPPORTED;
     if (n_pairs == 0) return ME_OK;  // nothing to read or write; pointers may be NULL
     if (!cur || !ref || !mv || !sad || !nsp) return ME_EINVAL;
     if (!aligned(cur, 4) || !aligned(ref, 4) || (pair_stride & 3)) return ME_EINVAL;
@@ -212,22 +214,22 @@ ME_EXPORT int me_search(const uint8_t* cur, const uint8_t* ref, int32_t width, i
         const FrameArgs a = frame_args(cur, ref, width, height, pitch, pair_stride, block, range, 1, 1);
         const long long grid = (long long)a.bw * a.bh * n_pairs;
         const int nt = fs_threads(range);
-        const bool j4 = fs_rows_per_item(range) == 4;
+        const bool split = fs_split(range);
         int16_t* mvp = reinterpret_cast<int16_t*>(mv);
         if (block == 16) {
-            if (j4)
-                hipLaunchKernelGGL((k_fs<16, 4>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<16>(range), st, a, mvp,
-                                   sad, nsp, sse);
+            if (split)
+                hipLaunchKernelGGL((k_fs<16, true>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<16>(range), st, a,
+                                   mvp, sad, nsp, sse);
             else
-                hipLaunchKernelGGL((k_fs<16, 1>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<16>(range), st, a, mvp,
-                                   sad, nsp, sse);
+                hipLaunchKernelGGL((k_fs<16, false>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<16>(range), st, a,
+                                   mvp, sad, nsp, sse);
         } else {
-            if (j4)
-                hipLaunchKernelGGL((k_fs<8, 4>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<8>(range), st, a, mvp,
-                                   sad, nsp, sse);
+            if (split)
+                hipLaunchKernelGGL((k_fs<8, true>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<8>(range), st, a,
+                                   mvp, sad, nsp, sse);
             else
-                hipLaunchKernelGGL((k_fs<8, 1>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<8>(range), st, a, mvp,
-                                   sad, nsp, sse);
+                hipLaunchKernelGGL((k_fs<8, false>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<8>(range), st, a,
+                                   mvp, sad, nsp, sse);
         }
         return launched();
     }
@@ -291,19 +293,19 @@ ME_EXPORT int me_mvp_stats(const uint8_t* cur, const uint8_t* ref, int32_t width
     const int chunk = (int)((total + 4095) / 4096);
     const unsigned grid = (unsigned)((total + chunk - 1) / chunk);
     const int nt = fs_threads(range);
-    const bool j4 = fs_rows_per_item(range) == 4;
+    const bool split = fs_split(range);
     const MvpCounts mc{hist, d1, d2, nullptr};
     const size_t hash = 4 * (size_t)mvp_hash_words();
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const int tb = (int)total;
     if (block == 16) {
         const size_t lds = fs_lds_bytes<16>(range) + hash;
-        if (j4) hipLaunchKernelGGL((k_fs_stats<16, 4>), dim3(grid), dim3(nt), lds, st, a, mc, tb, chunk);
-        else hipLaunchKernelGGL((k_fs_stats<16, 1>), dim3(grid), dim3(nt), lds, st, a, mc, tb, chunk);
+        if (split) hipLaunchKernelGGL((k_fs_stats<16, true>), dim3(grid), dim3(nt), lds, st, a, mc, tb, chunk);
+        else hipLaunchKernelGGL((k_fs_stats<16, false>), dim3(grid), dim3(nt), lds, st, a, mc, tb, chunk);
     } else {
         const size_t lds = fs_lds_bytes<8>(range) + hash;
-        if (j4) hipLaunchKernelGGL((k_fs_stats<8, 4>), dim3(grid), dim3(nt), lds, st, a, mc, tb, chunk);
-        else hipLaunchKernelGGL((k_fs_stats<8, 1>), dim3(grid), dim3(nt), lds, st, a, mc, tb, chunk);
+        if (split) hipLaunchKernelGGL((k_fs_stats<8, true>), dim3(grid), dim3(nt), lds, st, a, mc, tb, chunk);
+        else hipLaunchKernelGGL((k_fs_stats<8, false>), dim3(grid), dim3(nt), lds, st, a, mc, tb, chunk);
     }
     return launched();
 }

@@ -131,11 +131,11 @@ Variant dcds_variant_r(int rpl, int wpg, int R) {
 Variant pick_variant(int kind, int B, int rpl, int wpg, int R) {
     if (kind == KIND_FS) {
         const size_t lds = (B == 16 ? fs_lds_bytes<16>(R) : fs_lds_bytes<8>(R)) + 16;
-        const bool j4 = fs_rows_per_item(R) == 4;
-        const void* fn = B == 16 ? (j4 ? reinterpret_cast<const void*>(&k_fs_batch<16, 4>)
-                                       : reinterpret_cast<const void*>(&k_fs_batch<16, 1>))
-                                 : (j4 ? reinterpret_cast<const void*>(&k_fs_batch<8, 4>)
-                                       : reinterpret_cast<const void*>(&k_fs_batch<8, 1>));
+        const bool split = fs_split(R);
+        const void* fn = B == 16 ? (split ? reinterpret_cast<const void*>(&k_fs_batch<16, true>)
+                                          : reinterpret_cast<const void*>(&k_fs_batch<16, false>))
+                                 : (split ? reinterpret_cast<const void*>(&k_fs_batch<8, true>)
+                                          : reinterpret_cast<const void*>(&k_fs_batch<8, false>));
         return Variant{fn, fs_threads(R), lds};
     }
     const int rc = range_class(R);

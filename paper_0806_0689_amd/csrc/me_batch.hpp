@@ -86,7 +86,7 @@ __global__ __launch_bounds__(64 * WPG) void k_dcds_batch(const BatchTable* __res
     }
 }
 
-template <int B, int J>
+template <int B, bool SPLIT>
 __global__ __launch_bounds__(256) void k_fs_batch(const BatchTable* __restrict__ tab, int* __restrict__ counter) {
     extern __shared__ uint32_t smem[];
     __shared__ int s_tile;
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(256) void k_fs_batch(const BatchTable* __restrict__
             const int by = r % jb.a.bh;
             const int pair = r / jb.a.bh;
             if (t != t0) __syncthreads();
-            fs_block<B, J>(smem, jb.a, pair, bx, by, jb.mv, jb.sad, jb.nsp, jb.sse, blockDim.x);
+            fs_block<B, SPLIT>(smem, jb.a, pair, bx, by, jb.mv, jb.sad, jb.nsp, jb.sse, blockDim.x);
         }
     }
 }

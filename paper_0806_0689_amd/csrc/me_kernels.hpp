@@ -7,17 +7,37 @@ namespace me {
 
 // Copies rows [ys, ys + rows) x words [xs/4, xs/4 + words) of a frame into
 // LDS; words outside the frame read as 0 (no valid candidate ever uses them).
+// xs and W are multiples of 4, so a word is wholly inside or outside.  A
+// thread steps its (row, word) position without dividing; every load reads a
+// clamped in-frame address (positions past the window too, whose values are
+// dropped), and four loads are issued before any is stored.
 __device__ __forceinline__ void stage_window(uint32_t* dst, const uint8_t* frame, int W, int H, int pitch, int xs,
                                              int ys, int rows, int words, int tid, int nthreads) {
+    constexpr int U = 4;
     const int n = rows * words;
-    for (int i = tid; i < n; i += nthreads) {
-        const int r = i / words;
-        const int w = i - r * words;
-        const int gx = xs + 4 * w, gy = ys + r;
-        uint32_t v = 0;
-        if (gx >= 0 && gx < W && gy >= 0 && gy < H)
-            v = *reinterpret_cast<const uint32_t*>(frame + (size_t)gy * pitch + gx);
-        dst[i] = v;
+    int r = tid / words, w = tid - r * words;
+    const int dr = nthreads / words, dw = nthreads - dr * words;
+    for (int i0 = tid; i0 < n; i0 += U * nthreads) {
+        uint32_t v[U];
+        bool in[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int gx = xs + 4 * w, gy = ys + r;
+            in[u] = gx >= 0 && gx < W && gy >= 0 && gy < H;
+            const int cx = min(max(gx, 0), W - 4), cy = min(max(gy, 0), H - 1);
+            // In-frame offset: below 2^31 (height * pitch is), with a 24-bit
+            // row product (pitch < 2^24 then, as height >= 8).
+            v[u] = *reinterpret_cast<const uint32_t*>(frame + (uint32_t)(__mul24(cy, pitch) + cx));
+            w += dw;
+            r += dr;
+            if (w >= words) {
+                w -= words;
+                ++r;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (i0 + u * nthreads < n) dst[i0 + u * nthreads] = in[u] ? v[u] : 0u;
     }
 }
 
@@ -33,18 +53,21 @@ __device__ __forceinline__ void stage_window(uint32_t* dst, const uint8_t* frame
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int fs_groups(int R) { return margin_words(R) + (R + 1 + 3) / 4; }
 __host__ __device__ constexpr int fs_window_words(int B, int R) { return fs_groups(R) + B / 4; }
-__host__ __device__ constexpr int fs_rows_per_item(int R) { return R <= 7 ? 1 : 4; }
+// Candidate rows are taken 4 at a time.
+__host__ __device__ constexpr int fs_row_groups(int R) { return (2 * R + 1 + 3) / 4; }
+__host__ __device__ constexpr int fs_window_rows(int B, int R) { return 4 * fs_row_groups(R) + B - 1; }
+// Up to +-7 a block has too few candidates to give 64 lanes 4 whole
+// candidate rows each: the block rows are split over a lane quad instead.
+__host__ __device__ constexpr bool fs_split(int R) { return R <= 7; }
 __host__ __device__ constexpr int fs_items(int R) {
-    return fs_groups(R) * ((2 * R + 1 + fs_rows_per_item(R) - 1) / fs_rows_per_item(R));
+    return fs_groups(R) * fs_row_groups(R) * (fs_split(R) ? 4 : 1);
 }
 __host__ __device__ constexpr int fs_threads(int R) {
     return fs_items(R) <= 64 ? 64 : (fs_items(R) <= 128 ? 128 : 256);
 }
 template <int B>
 __host__ __device__ constexpr size_t fs_lds_bytes(int R) {
-    const int J = fs_rows_per_item(R);
-    const int rows = ((2 * R + 1 + J - 1) / J) * J + B - 1;
-    return (size_t)4 * rows * fs_window_words(B, R) + 4 * 12;
+    return (size_t)4 * fs_window_rows(B, R) * fs_window_words(B, R) + 4 * 12;
 }
 
 __device__ __forceinline__ uint32_t fs_key(uint32_t s, int x, int y) {
@@ -100,17 +123,32 @@ __device__ __forceinline__ void mvp_add(uint32_t* tab, uint32_t key, uint32_t* g
     atomicAdd(&global[key], 1u);
 }
 
-// J candidate rows per item; nt threads per workgroup.  The block rows are
+// Keys one candidate into the running minima.
+// ST: also the minima over the CDS first-step cross (c1) and over the
+// central 5x5 square (c2), with the same keys.
+template <bool ST>
+__device__ __forceinline__ void fs_take(uint32_t s, int x, int y, int lox, int hix, int loy, int hiy, uint32_t& best,
+                                        uint32_t& c1, uint32_t& c2) {
+    const bool ok = x >= lox && x <= hix && y >= loy && y <= hiy;
+    const uint32_t kk = ok ? fs_key(s, x, y) : 0xFFFFFFFFu;
+    best = min(best, kk);
+    if (ST) {
+        const bool sq = abs(x) <= 2 && abs(y) <= 2;
+        c2 = min(c2, sq ? kk : 0xFFFFFFFFu);
+        c1 = min(c1, sq && (x == 0 || y == 0) ? kk : 0xFFFFFFFFu);
+    }
+}
+
+// 4 candidate rows per item; nt threads per workgroup.  The block rows are
 // taken V at a time (a runtime loop, so that only V rows of the current block
 // are live in scalar registers); each step reads the V + J - 1 reference rows
 // it needs from LDS.
-// ST: also the minima over the CDS first-step cross (c1) and over the
-// central 5x5 square (c2), with the same keys.
-template <int B, int J, bool ST>
+template <int B, bool ST>
 __device__ __forceinline__ uint32_t fs_items_min(const uint32_t* win, int WD, int G, int items, int R, int MW,
                                                  const uint32_t* cur, int cpw, int lox, int hix, int loy, int hiy,
                                                  int nt, uint32_t& c1, uint32_t& c2) {
     constexpr int K = B / 4;
+    constexpr int J = 4;
     constexpr int V = 4;
     constexpr int Q = V + J - 1;
     uint32_t best = 0xFFFFFFFFu;
@@ -142,31 +180,79 @@ __device__ __forceinline__ uint32_t fs_items_min(const uint32_t* win, int WD, in
                                                                  c[u][k], acc[j]);
         }
 #pragma unroll
-        for (int j = 0; j < J; ++j) {
-            const int y = y0 + j - R;
+        for (int j = 0; j < J; ++j)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int x = -4 * MW + 4 * g + i;
-                const uint32_t s = (uint32_t)(acc[j] >> (16 * i)) & 0xFFFFu;
-                const bool ok = x >= lox && x <= hix && y >= loy && y <= hiy;
-                const uint32_t kk = ok ? fs_key(s, x, y) : 0xFFFFFFFFu;
-                best = min(best, kk);
-                if (ST) {
-                    const bool sq = abs(x) <= 2 && abs(y) <= 2;
-                    c2 = min(c2, sq ? kk : 0xFFFFFFFFu);
-                    c1 = min(c1, sq && (x == 0 || y == 0) ? kk : 0xFFFFFFFFu);
-                }
-            }
+            for (int i = 0; i < 4; ++i)
+                fs_take<ST>((uint32_t)(acc[j] >> (16 * i)) & 0xFFFFu, -4 * MW + 4 * g + i, y0 + j - R, lox, hix, loy,
+                            hiy, best, c1, c2);
+    }
+    return best;
+}
+
+// Small ranges (fs_split): an item is (group of 4 candidate rows, x group g,
+// quarter q of the block rows), q fastest, so the four quarters of one
+// (row group, g) are one lane quad.  A lane sums its B/4 block rows for the
+// 4 candidate rows x 4 shifts; two DPP steps add the quad's partial sums
+// (each 16-bit field holds a block SAD, at most 255 B^2 < 2^16), after which
+// lane q keys candidate row q.  The block rows differ within a quad, so
+// they are vector loads here.  items is a multiple of 4 and at most nt.
+template <int B, bool ST>
+__device__ __forceinline__ uint32_t fs_items_min_split(const uint32_t* win, int WD, int G, int items, int R, int MW,
+                                                       const uint32_t* cur, int cpw, int lox, int hix, int loy,
+                                                       int hiy, uint32_t& c1, uint32_t& c2) {
+    constexpr int K = B / 4;
+    constexpr int J = 4;
+    constexpr int V = B / 4;  // block rows per quarter
+    constexpr int Q = V + J - 1;
+    uint32_t best = 0xFFFFFFFFu;
+    const int it = threadIdx.x;
+    if (it < items) {  // whole quads only
+        const int q = it & 3, item = it >> 2;
+        const int yg = item / G, g = item - yg * G;
+        const int y0 = yg * J;
+        const int vb = q * V;
+        uint32_t c[V][K];
+#pragma unroll
+        for (int u = 0; u < V; ++u)
+#pragma unroll
+            for (int k = 0; k < K; ++k) c[u][k] = cur[(vb + u) * cpw + k];
+        uint32_t d[Q][K + 1];
+#pragma unroll
+        for (int r = 0; r < Q; ++r)
+#pragma unroll
+            for (int k = 0; k <= K; ++k) d[r][k] = win[(y0 + vb + r) * WD + g + k];
+        uint64_t acc[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) acc[j] = 0;
+#pragma unroll
+        for (int u = 0; u < V; ++u)
+#pragma unroll
+            for (int j = 0; j < J; ++j)
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    acc[j] = __builtin_amdgcn_qsad_pk_u16_u8(((uint64_t)d[u + j][k + 1] << 32) | d[u + j][k], c[u][k],
+                                                             acc[j]);
+        uint32_t lo = 0, hi = 0;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const uint32_t l = group_sum<4>((uint32_t)acc[j]), h = group_sum<4>((uint32_t)(acc[j] >> 32));
+            lo = q == j ? l : lo;
+            hi = q == j ? h : hi;
         }
+        const int y = y0 + q - R;
+        fs_take<ST>(lo & 0xFFFFu, -4 * MW + 4 * g, y, lox, hix, loy, hiy, best, c1, c2);
+        fs_take<ST>(lo >> 16, -4 * MW + 4 * g + 1, y, lox, hix, loy, hiy, best, c1, c2);
+        fs_take<ST>(hi & 0xFFFFu, -4 * MW + 4 * g + 2, y, lox, hix, loy, hiy, best, c1, c2);
+        fs_take<ST>(hi >> 16, -4 * MW + 4 * g + 3, y, lox, hix, loy, hiy, best, c1, c2);
     }
     return best;
 }
 
 // One block of one frame pair; all nt threads of the workgroup call it.
-// J = fs_rows_per_item(R) (checked by the caller).
+// SPLIT = fs_split(R) (checked by the caller).
 // ST: instead of the per-block outputs (mv, sad, nsp may be NULL), count
 // the block in the MVP statistics.
-template <int B, int J, bool ST = false>
+template <int B, bool SPLIT, bool ST = false>
 __device__ __forceinline__ void fs_block(uint32_t* smem, const FrameArgs& a, int pair, int bx, int by,
                                          int16_t* __restrict__ mv, uint32_t* __restrict__ sad,
                                          uint32_t* __restrict__ nsp, uint32_t* __restrict__ sse, int nt,
@@ -175,26 +261,28 @@ __device__ __forceinline__ void fs_block(uint32_t* smem, const FrameArgs& a, int
     const int MW = margin_words(R);
     const int G = fs_groups(R);
     const int WD = fs_window_words(B, R);
-    const int DG = (2 * R + 1 + J - 1) / J;
-    const int WR = DG * J + B - 1;
+    const int WR = fs_window_rows(B, R);
     uint32_t* win = smem;
     uint32_t* part = smem + WR * WD;
 
     const uint8_t* curf = a.cur + (long long)pair * a.pair_stride;
     const uint8_t* reff = a.ref + (long long)pair * a.pair_stride;
     const int x0 = bx * B, y0 = by * B;
-    stage_window(win, reff, a.W, a.H, a.pitch, x0 - 4 * MW, y0 - R, WR, WD, threadIdx.x, nt);
-    // The current block is read straight from global memory: the same words
-    // for every lane (scalar loads).
+    // The current block is read straight from global memory (with whole
+    // candidate rows per lane, the same words for every lane: scalar loads).
     const uint32_t* cur = reinterpret_cast<const uint32_t*>(curf + (size_t)y0 * a.pitch + x0);
+    stage_window(win, reff, a.W, a.H, a.pitch, x0 - 4 * MW, y0 - R, WR, WD, threadIdx.x, nt);
     __syncthreads();
 
     const int lox = max(-R, -x0), hix = min(R, a.W - B - x0);
     const int loy = max(-R, -y0), hiy = min(R, a.H - B - y0);
-    const int items = G * DG;
+    const int items = fs_items(R);
     uint32_t c1 = 0xFFFFFFFFu, c2 = 0xFFFFFFFFu;
-    uint32_t best =
-        fs_items_min<B, J, ST>(win, WD, G, items, R, MW, cur, a.pitch / 4, lox, hix, loy, hiy, nt, c1, c2);
+    uint32_t best;
+    if constexpr (SPLIT)
+        best = fs_items_min_split<B, ST>(win, WD, G, items, R, MW, cur, a.pitch / 4, lox, hix, loy, hiy, c1, c2);
+    else
+        best = fs_items_min<B, ST>(win, WD, G, items, R, MW, cur, a.pitch / 4, lox, hix, loy, hiy, nt, c1, c2);
     // Workgroup minimum: every thread reads the per-wave minima.
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
@@ -259,7 +347,7 @@ __device__ __forceinline__ void fs_block(uint32_t* smem, const FrameArgs& a, int
     }
 }
 
-template <int B, int J>
+template <int B, bool SPLIT>
 __global__ __launch_bounds__(256) void k_fs(FrameArgs a, int16_t* __restrict__ mv, uint32_t* __restrict__ sad,
                                             uint32_t* __restrict__ nsp, uint32_t* __restrict__ sse) {
     extern __shared__ uint32_t smem[];
@@ -268,18 +356,17 @@ __global__ __launch_bounds__(256) void k_fs(FrameArgs a, int16_t* __restrict__ m
     t /= a.bw;
     const int by = t % a.bh;
     const int pair = t / a.bh;
-    fs_block<B, J>(smem, a, pair, bx, by, mv, sad, nsp, sse, blockDim.x);
+    fs_block<B, SPLIT>(smem, a, pair, bx, by, mv, sad, nsp, sse, blockDim.x);
 }
 
 // Persistent: workgroup w takes blocks [w chunk, (w + 1) chunk) of the
 // flattened (pair, by, bx) space.  LDS: window, reduction scratch, then the
 // hash tables.
-template <int B, int J>
+template <int B, bool SPLIT>
 __global__ __launch_bounds__(256) void k_fs_stats(FrameArgs a, MvpCounts mc, int total, int chunk) {
     extern __shared__ uint32_t smem[];
     const int R = a.R;
-    const int DG = (2 * R + 1 + J - 1) / J;
-    mc.lds = smem + (DG * J + B - 1) * fs_window_words(B, R) + 12;
+    mc.lds = smem + fs_window_rows(B, R) * fs_window_words(B, R) + 12;
     for (int i = threadIdx.x; i < mvp_hash_words(); i += blockDim.x)
         mc.lds[i] = (i / kMvpSlots) % 2 == 0 ? kMvpEmpty : 0u;
     const int lo = blockIdx.x * chunk, hi = min(total, lo + chunk);
@@ -290,7 +377,7 @@ __global__ __launch_bounds__(256) void k_fs_stats(FrameArgs a, MvpCounts mc, int
         t /= a.bw;
         const int by = t % a.bh;
         const int pair = t / a.bh;
-        fs_block<B, J, true>(smem, a, pair, bx, by, nullptr, nullptr, nullptr, nullptr, blockDim.x, mc);
+        fs_block<B, SPLIT, true>(smem, a, pair, bx, by, nullptr, nullptr, nullptr, nullptr, blockDim.x, mc);
     }
     __syncthreads();
     uint32_t* const dst[3] = {mc.hist, mc.d1, mc.d2};

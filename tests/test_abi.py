@@ -80,6 +80,8 @@ def _search_dcds_sse(*a):
     (dict(n_pairs=0), me.ME_OK),              # empty input: nothing to do
     (dict(n_pairs=0, cur=None, mv=None), me.ME_OK),
     (dict(n_pairs=0, block=12), me.ME_EUNSUPPORTED),
+    (dict(height=65536, pitch=32768, n_pairs=0), me.ME_EUNSUPPORTED),  # one frame of 2 GiB
+    (dict(height=32768, pitch=65532, n_pairs=0), me.ME_OK),             # just below 2^31 bytes
 ])
 def test_frame_argument_checks(fn, kw, status):
     assert _frame_call(fn, **kw) == status
