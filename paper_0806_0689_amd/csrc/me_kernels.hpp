@@ -123,19 +123,34 @@ __device__ __forceinline__ void mvp_add(uint32_t* tab, uint32_t key, uint32_t* g
     atomicAdd(&global[key], 1u);
 }
 
+// The position part of a key splits into a column part and a row part:
+// (|x| + |y|) << 7 | (y + 31) << 1 | (x > 0) = X(x) + Y(y) with
+// X = |x| << 7 | (x > 0) and Y = |y| << 7 + (y + 31) << 1 (the fields never
+// carry into each other), so a lane builds the parts of its 4 columns and
+// 4 rows once and keys each candidate with an add.
+struct FsAxis {
+    uint32_t part;
+    bool ok, sq, zero;  // inside the candidate set; within +-2; zero
+};
+__device__ __forceinline__ FsAxis fs_axis_x(int x, int lo, int hi) {
+    return FsAxis{((uint32_t)abs(x) << 7) | (x > 0 ? 1u : 0u), x >= lo && x <= hi, abs(x) <= 2, x == 0};
+}
+__device__ __forceinline__ FsAxis fs_axis_y(int y, int lo, int hi) {
+    return FsAxis{((uint32_t)abs(y) << 7) + ((uint32_t)(y + 31) << 1), y >= lo && y <= hi, abs(y) <= 2, y == 0};
+}
+
 // Keys one candidate into the running minima.
 // ST: also the minima over the CDS first-step cross (c1) and over the
 // central 5x5 square (c2), with the same keys.
 template <bool ST>
-__device__ __forceinline__ void fs_take(uint32_t s, int x, int y, int lox, int hix, int loy, int hiy, uint32_t& best,
-                                        uint32_t& c1, uint32_t& c2) {
-    const bool ok = x >= lox && x <= hix && y >= loy && y <= hiy;
-    const uint32_t kk = ok ? fs_key(s, x, y) : 0xFFFFFFFFu;
+__device__ __forceinline__ void fs_take(uint32_t s, const FsAxis& ax, const FsAxis& ay, uint32_t& best, uint32_t& c1,
+                                        uint32_t& c2) {
+    const uint32_t kk = ax.ok && ay.ok ? (s << 13) + ax.part + ay.part : 0xFFFFFFFFu;
     best = min(best, kk);
     if (ST) {
-        const bool sq = abs(x) <= 2 && abs(y) <= 2;
+        const bool sq = ax.sq && ay.sq;
         c2 = min(c2, sq ? kk : 0xFFFFFFFFu);
-        c1 = min(c1, sq && (x == 0 || y == 0) ? kk : 0xFFFFFFFFu);
+        c1 = min(c1, sq && (ax.zero || ay.zero) ? kk : 0xFFFFFFFFu);
     }
 }
 
@@ -179,12 +194,16 @@ __device__ __forceinline__ uint32_t fs_items_min(const uint32_t* win, int WD, in
                         acc[j] = __builtin_amdgcn_qsad_pk_u16_u8(((uint64_t)d[u + j][k + 1] << 32) | d[u + j][k],
                                                                  c[u][k], acc[j]);
         }
+        FsAxis ax[4], ay[J];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ax[i] = fs_axis_x(-4 * MW + 4 * g + i, lox, hix);
+#pragma unroll
+        for (int j = 0; j < J; ++j) ay[j] = fs_axis_y(y0 + j - R, loy, hiy);
 #pragma unroll
         for (int j = 0; j < J; ++j)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                fs_take<ST>((uint32_t)(acc[j] >> (16 * i)) & 0xFFFFu, -4 * MW + 4 * g + i, y0 + j - R, lox, hix, loy,
-                            hiy, best, c1, c2);
+                fs_take<ST>((uint32_t)(acc[j] >> (16 * i)) & 0xFFFFu, ax[i], ay[j], best, c1, c2);
     }
     return best;
 }
@@ -239,11 +258,11 @@ __device__ __forceinline__ uint32_t fs_items_min_split(const uint32_t* win, int 
             lo = q == j ? l : lo;
             hi = q == j ? h : hi;
         }
-        const int y = y0 + q - R;
-        fs_take<ST>(lo & 0xFFFFu, -4 * MW + 4 * g, y, lox, hix, loy, hiy, best, c1, c2);
-        fs_take<ST>(lo >> 16, -4 * MW + 4 * g + 1, y, lox, hix, loy, hiy, best, c1, c2);
-        fs_take<ST>(hi & 0xFFFFu, -4 * MW + 4 * g + 2, y, lox, hix, loy, hiy, best, c1, c2);
-        fs_take<ST>(hi >> 16, -4 * MW + 4 * g + 3, y, lox, hix, loy, hiy, best, c1, c2);
+        const FsAxis ay = fs_axis_y(y0 + q - R, loy, hiy);
+        fs_take<ST>(lo & 0xFFFFu, fs_axis_x(-4 * MW + 4 * g, lox, hix), ay, best, c1, c2);
+        fs_take<ST>(lo >> 16, fs_axis_x(-4 * MW + 4 * g + 1, lox, hix), ay, best, c1, c2);
+        fs_take<ST>(hi & 0xFFFFu, fs_axis_x(-4 * MW + 4 * g + 2, lox, hix), ay, best, c1, c2);
+        fs_take<ST>(hi >> 16, fs_axis_x(-4 * MW + 4 * g + 3, lox, hix), ay, best, c1, c2);
     }
     return best;
 }
