@@ -397,7 +397,7 @@ __global__ __launch_bounds__(256) void k_head_export(const float* __restrict__ h
 // ---------------------------------------------------------------------------
 constexpr int kTB = 8;
 constexpr int kN3 = kTB + 2, kN2 = 2 * kN3 + 1, kN1 = 2 * kN2 + 1, kN0 = kN1 + 2;
-constexpr int kP0 = 4, kP1 = 20, kP2 = 40, kP3 = 40;  // pixel pitches
+constexpr int kP0 = 4, kP1 = 20, kP2 = 44, kP3 = 40;  // pixel pitches
 constexpr int kSz0 = kN0 * kN0 * kP0, kSz1 = kN1 * kN1 * kP1, kSz2 = kN2 * kN2 * kP2, kSz3 = kN3 * kN3 * kP3;
 // Weights in LDS: layer l as [COUT][KP + 4] bf16.
 __host__ __device__ constexpr int wrow(int l) { return pad16(9 * kLayers[l].cin) + 4; }
