@@ -319,8 +319,8 @@ def main():
                     help="first copy 256 MiB device-to-device (a known-size kernel for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(blocks are independent; see the design notes on sharding).", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path "
+              "(blocks are independent; sharding across GPUs needs no exchange).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

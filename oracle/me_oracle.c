@@ -263,7 +263,7 @@ static int check_frame_args(const uint8_t *cur, const uint8_t *ref, int W, int H
 /* Full search: every point of V; the motion vector is the lexicographic    */
 /* minimum of (SAD, |dx|+|dy|, dy, dx).  The paper assumes a unique FS      */
 /* optimum; this tie order (centre-biased, then top-most, then left-most)   */
-/* is the build's reading.                                                    */
+/* is the reading taken here.                                                 */
 /* mv: 2 int16 per block (dx, dy); sad, nsp: one uint32 per block; raster. */
 /* ------------------------------------------------------------------------ */
 int oracle_fs(const uint8_t *cur, const uint8_t *ref, int W, int H, int pitch, int B, int R,

@@ -1,7 +1,7 @@
 """The proposer's GPU kernels against the fp64 oracle (oracle/cnn.py), which
 mirrors the GPU's bf16 storage points.  What remains between the two is fp32
 accumulation order and the rare bf16 rounding decision it flips; the bounds
-below follow from that (learned start)."""
+below follow from that (one flip moves a value by at most 2^-8 of itself)."""
 import numpy as np
 import pytest
 

@@ -1,7 +1,7 @@
 """What the trained proposer gains over DCDS without it, on held-out seeds
 (never seen in training): the learned start must keep mean SAD within 1% of
 plain DCDS and is expected to save search points; every block stays no better
-than FS (the judge).  Uses the committed checkpoint written by
+than FS (the exhaustive reference).  Uses the committed checkpoint written by
 paper_0806_0689_amd/train.py."""
 import os
 

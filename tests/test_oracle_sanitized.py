@@ -1,8 +1,8 @@
 """The C oracle under AddressSanitizer and UndefinedBehaviorSanitizer (host
-code only, built with gcc): a driver runs every entry point over frames with
+code only, built with gcc): a test program runs every entry point over frames with
 edge blocks, both block sizes, ranges 1..7, learned starts at and beyond the
 window corners, both DCDS variants and cost surfaces with holes.  Any
-out-of-bounds access, leak or undefined operation aborts the driver."""
+out-of-bounds access, leak or undefined operation aborts the test program."""
 import os
 import shutil
 import subprocess
@@ -11,7 +11,7 @@ import pytest
 
 ORACLE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle", "me_oracle.c")
 
-DRIVER = r"""
+PROGRAM = r"""
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -82,9 +82,9 @@ int main(void) {
 
 
 def build_and_run(tmp_path, source):
-    drv = tmp_path / "driver.c"
+    drv = tmp_path / "prog.c"
     drv.write_text(source)
-    exe = tmp_path / "driver"
+    exe = tmp_path / "prog"
     cmd = ["gcc", "-O1", "-g", "-std=c99", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
            "-fno-omit-frame-pointer", "-o", str(exe), str(drv), ORACLE]
     try:
@@ -99,17 +99,17 @@ def build_and_run(tmp_path, source):
 
 @pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not found")
 def test_oracle_under_asan_ubsan(tmp_path):
-    r = build_and_run(tmp_path, DRIVER)
+    r = build_and_run(tmp_path, PROGRAM)
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
     assert "rc 0" in r.stdout
 
 
 @pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not found")
 def test_the_instrumentation_is_live(tmp_path):
-    """A one-byte write past a frame buffer, planted in a copy of the driver,
+    """A one-byte write past a frame buffer, planted in a copy of the program,
     must be reported: the clean run above then means something."""
-    planted = DRIVER.replace("free(cur); free(ref);", "cur[pitch * H] = 1; free(cur); free(ref);")
-    assert planted != DRIVER
+    planted = PROGRAM.replace("free(cur); free(ref);", "cur[pitch * H] = 1; free(cur); free(ref);")
+    assert planted != PROGRAM
     r = build_and_run(tmp_path, planted)
     assert r.returncode != 0
     assert "heap-buffer-overflow" in r.stderr
