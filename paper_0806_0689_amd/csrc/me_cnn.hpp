@@ -517,8 +517,7 @@ __device__ __forceinline__ void conv_tile(const uint16_t* in, uint16_t* out, flo
 // multiples of 4 pixels, so the 4 pixels are all inside the frame or all
 // outside; outside items read a clamped in-frame address and use zeros, so
 // every load of an item is issued before any is used.  Rows are 4-byte
-// aligned, which is all a 16-byte global load needs.
-// 16 bytes at a 4-byte aligned address (one dwordx4 load).
+// aligned, which is all a 16-byte global load (u32x4a4: one dwordx4) needs.
 typedef uint32_t u32x4a4 __attribute__((ext_vector_type(4), aligned(4)));
 constexpr int kInG = (kN0 + 3) / 4;  // items per row; the last holds kN0 - 4 (kInG - 1) tile pixels
 constexpr int kInItems = kN0 * kInG;
