@@ -119,6 +119,39 @@ def test_cif_multi_pair_call():
         assert_same(me.fullsearch(tc, tr, B, 7), oracle_pairs(oracle.fullsearch, cur, ref, B, 7), "cif fs")
 
 
+@pytest.mark.parametrize("case", range(24))
+def test_random_configurations(case):
+    """Seeded random shapes, ranges, block sizes, pair counts, row pitches and
+    4-byte frame offsets: every search against the oracle."""
+    rng = np.random.default_rng(1000 + case)
+    B = int(rng.choice([8, 16]))
+    R = int(rng.integers(1, 32))
+    bh, bw, P = int(rng.integers(1, 9)), int(rng.integers(1, 13)), int(rng.integers(1, 4))
+    H, W = bh * B, bw * B
+    pad = 4 * int(rng.integers(0, 5))      # extra row bytes
+    off = 4 * int(rng.integers(0, 4))      # frame start offset inside its row
+    kind = str(rng.choice(["shifted", "uniform", "checker"]))
+    frames = [random_pair(H, W, B, min(R, 7), seed=2000 + case * 10 + p, kind=kind) for p in range(P)]
+    cur = np.stack([f[0] for f in frames])
+    ref = np.stack([f[1] for f in frames])
+    big = np.zeros((2, P, H, off + W + pad), np.uint8)
+    big[0, :, :, off:off + W], big[1, :, :, off:off + W] = cur, ref
+    tb = to_dev(big)
+    tc, tr = tb[0, :, :, off:off + W], tb[1, :, :, off:off + W]
+    label = "random case %d B=%d R=%d %dx%d P=%d pad=%d off=%d %s" % (case, B, R, H, W, P, pad, off, kind)
+    say(label)
+    assert_same(me.fullsearch(tc, tr, B, R), oracle_pairs(oracle.fullsearch, cur, ref, B, R), label + " fs")
+    assert_same(me.dcds(tc, tr, B, R), oracle_pairs(oracle.dcds, cur, ref, B, R), label + " dcds")
+    assert_same(me.dcds(tc, tr, B, R, algo=me.ME_ALGO_DCDS_S),
+                oracle_pairs(oracle.dcds, cur, ref, B, R, variant=oracle.VARIANT_DCDS_S), label + " dcds_s")
+    start = rng.integers(-R - 2, R + 3, (P, bh, bw, 2)).astype(np.int16)
+    orient = rng.integers(0, 2, (P, bh, bw)).astype(np.uint8)
+    got = me.dcds(tc, tr, B, R, start=to_dev(start), orient=to_dev(orient))
+    exp = tuple(np.stack(x) for x in zip(*[oracle.dcds(cur[p], ref[p], B, R, start=start[p], orient=orient[p])
+                                            for p in range(P)]))
+    assert_same(got, exp, label + " seeded")
+
+
 def test_pitch_wider_than_frame():
     cur, ref = random_pair(64, 96, 16, 7, seed=9)
     big_c = np.zeros((64, 128), np.uint8)
