@@ -175,13 +175,15 @@ __device__ SearchOut dcds_search(const Ev& ev, int R, const Bounds& bd, uint32_t
         const bool vF = (s ? rap : ram) >= 2;
         const bool vNm = rc.pm(t) != 0, vNp = rc.pp(t) != 0;
         const int arm2 = t ? 2 * rs : 2, perp = t ? 1 : rs;
-        uint32_t cNm, cNp;
-        ev.pair(ca + (s ? arm2 : -arm2), ca - perp, cF, cNm);
-        cNp = ev.one(ca + perp);
         {
+            // Marked before the evaluation, so that no masked store splits
+            // the sums' DPP steps (which then fold into their adds).
             const int ko = t ? kv : kh;
             mark((g == 0 && vF) || (g == 1 && vNm) || (g == 2 && vNp), kc + ((g == 0 && !s) ? -ko : ko));
         }
+        uint32_t cNm, cNp;
+        ev.pair(ca + (s ? arm2 : -arm2), ca - perp, cF, cNm);
+        cNp = ev.one(ca + perp);
         uint32_t mm = cc8;
         mm = min(mm, key(vF, cF, 1u));
         mm = min(mm, key(vNm, cNm, 3u));
@@ -229,12 +231,12 @@ __device__ SearchOut dcds_search(const Ev& ev, int R, const Bounds& bd, uint32_t
         r1 = r1 && use1;
     }
     const int arm = t ? rs : 1;
-    uint32_t mc0, mc1;
-    ev.pair(ca - arm, ca + arm, mc0, mc1);
     {
         const int ka = t ? S : 1;
         mark((g == 0 && r0) || (g == 1 && r1), g == 0 ? kc - ka : kc + ka);
     }
+    uint32_t mc0, mc1;
+    ev.pair(ca - arm, ca + arm, mc0, mc1);
     uint32_t mf = cc8;
     mf = min(mf, key(r0, mc0, 1u));
     mf = min(mf, key(r1, mc1, 2u));
