@@ -64,36 +64,73 @@ __host__ __device__ constexpr size_t dcds_lds_bytes(int R) {
     return (size_t)4 * (G::WIN_WORDS + G::BPW * WPG * bitmap_words(R));
 }
 
-// Copies the tile window (rows of WB bytes, LDS pitch WDW words) of the
-// reference frame into LDS.  VEC: 16-byte global loads (frame base, pitch and
-// width multiples of 16); otherwise 4-byte loads.  Words outside the frame
-// read as 0; no valid candidate uses them.
-template <int WB, int WDW, int WR, int NT, bool VEC>
-__device__ __forceinline__ void stage(uint32_t* win, const uint8_t* frame, int W, int H, int pitch, int xs, int ys) {
-    constexpr int CH = VEC ? 16 : 4;       // bytes per chunk
-    constexpr int CPR = WB / CH;           // chunks per row
-    constexpr int RSTEP = NT / CPR;        // rows per pass
-    const int t = threadIdx.x;
-    const int c = t % CPR, r0 = t / CPR;
-    if (r0 >= RSTEP) return;
+// Stages column c (CH bytes at window x offset c * CH) of the window rows
+// r0, r0 + RS, ... (NP of them) into LDS.  Only the last of them can reach
+// past the window; it is replaced by row WR - 1, which then gets the same
+// chunk from two threads (so no store is conditional).  The
+// window's x origin xs and W are multiples of CH, so a chunk lies wholly
+// inside or outside the frame; chunks outside read as 0 (no valid candidate
+// uses them).  Every load reads a clamped in-frame address, at a 32-bit
+// offset (a frame spans less than 2^31 bytes), and up to four loads are in
+// flight before the first store.
+template <int CH, int WDW, int WR, int RS, int NP>
+__device__ __forceinline__ void stage_column(uint32_t* win, const uint8_t* frame, int W, int H, int pitch, int xs,
+                                             int ys, int c, int r0) {
+    constexpr int CW = CH / 4;  // words per chunk
+    constexpr int U = 4;        // loads per batch
     const int gx = xs + c * CH;
     const bool xin = gx >= 0 && gx < W;
-    for (int r = r0; r < WR; r += RSTEP) {
-        const int gy = ys + r;
-        const bool in = xin && gy >= 0 && gy < H;
-        uint32_t* dst = win + r * WDW + c * (CH / 4);
-        if constexpr (VEC) {
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (in) v = *reinterpret_cast<const uint4*>(frame + (size_t)gy * pitch + gx);
-            dst[0] = v.x;
-            dst[1] = v.y;
-            dst[2] = v.z;
-            dst[3] = v.w;
-        } else {
-            uint32_t v = 0u;
-            if (in) v = *reinterpret_cast<const uint32_t*>(frame + (size_t)gy * pitch + gx);
-            dst[0] = v;
+    const int cx = min(max(gx, 0), W - CH);
+    for (int p0 = 0; p0 < NP; p0 += U) {
+        uint32_t v[U][CW];
+        int r[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            r[u] = r0 + (p0 + u) * RS;
+            if (p0 + u == NP - 1) r[u] = min(r[u], WR - 1);
+            const int cy = min(max(ys + r[u], 0), H - 1);
+            const uint8_t* src = frame + (uint32_t)(cy * pitch + cx);
+            if (p0 + u < NP) {
+                if constexpr (CW == 4) {
+                    const uint4 q = *reinterpret_cast<const uint4*>(src);
+                    v[u][0] = q.x;
+                    v[u][1] = q.y;
+                    v[u][2] = q.z;
+                    v[u][3] = q.w;
+                } else {
+                    v[u][0] = *reinterpret_cast<const uint32_t*>(src);
+                }
+            }
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int gy = ys + r[u];
+            const bool in = xin && gy >= 0 && gy < H;
+            if (p0 + u < NP) {
+                uint32_t* dst = win + r[u] * WDW + c * CW;
+#pragma unroll
+                for (int k = 0; k < CW; ++k) dst[k] = in ? v[u][k] : 0u;
+            }
+        }
+    }
+}
+
+// Copies the tile window (WR rows of WB bytes, LDS pitch WDW words) of the
+// reference frame into LDS with NT threads.  VEC: 16-byte chunks (frame base,
+// pitch and width multiples of 16); otherwise 4-byte chunks.  A thread keeps
+// one column over every RS-th row while a row has at most NT chunks, else it
+// takes whole columns.
+template <int WB, int WDW, int WR, int NT, bool VEC>
+__device__ __forceinline__ void stage(uint32_t* win, const uint8_t* frame, int W, int H, int pitch, int xs, int ys) {
+    constexpr int CH = VEC ? 16 : 4;  // bytes per chunk
+    constexpr int CPR = WB / CH;      // chunks per row
+    const int t = threadIdx.x;
+    if constexpr (CPR <= NT) {
+        constexpr int RS = NT / CPR;  // rows per pass
+        const int c = t % CPR, r0 = t / CPR;
+        if (r0 < RS) stage_column<CH, WDW, WR, RS, (WR + RS - 1) / RS>(win, frame, W, H, pitch, xs, ys, c, r0);
+    } else {
+        for (int c = t; c < CPR; c += NT) stage_column<CH, WDW, WR, 1, WR>(win, frame, W, H, pitch, xs, ys, c, 0);
     }
 }
 
@@ -256,10 +293,6 @@ __device__ __forceinline__ void dcds_tile(uint32_t* smem, const FrameArgs& a, in
     const int X0 = tx * G::TW, Y0 = ty * G::TH;
 
     const bool vec = (flags & DCDS_VEC16) != 0;
-    if (vec)
-        stage<G::NEED * 4, G::WDW, G::WR, 64 * WPG, true>(win, reff, a.W, a.H, a.pitch, X0 - G::ML, Y0 - G::MR);
-    else
-        stage<G::NEED * 4, G::WDW, G::WR, 64 * WPG, false>(win, reff, a.W, a.H, a.pitch, X0 - G::ML, Y0 - G::MR);
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int b = lane / L, g = lane % L;
@@ -279,12 +312,11 @@ __device__ __forceinline__ void dcds_tile(uint32_t* smem, const FrameArgs& a, in
     }
     const int bx = tx * G::BPW + bxl, by = ty * WPG + byl;
     const bool exists = bx < a.bw && by < a.bh;
-    uint32_t* bm = bms + (wave * G::BPW + b) * BMW;
-    for (int i = g; i < BMW; i += L) bm[i] = 0u;
-
     FrameEval<B, RPL, G::WDW> ev;
     ev.a00 = (int)lds_offset(win) + (G::MR + byl * B + row0<RPL, L>(g)) * (G::WDW * 4) + G::ML + bxl * B;
     const int x0 = bx * B, y0 = by * B;
+    // The block's rows are loaded first, so that they are in flight while
+    // the window is staged.
     if (exists) {
 #pragma unroll
         for (int j = 0; j < RPL; ++j) {
@@ -301,6 +333,12 @@ __device__ __forceinline__ void dcds_tile(uint32_t* smem, const FrameArgs& a, in
             }
         }
     }
+    if (vec)
+        stage<G::NEED * 4, G::WDW, G::WR, 64 * WPG, true>(win, reff, a.W, a.H, a.pitch, X0 - G::ML, Y0 - G::MR);
+    else
+        stage<G::NEED * 4, G::WDW, G::WR, 64 * WPG, false>(win, reff, a.W, a.H, a.pitch, X0 - G::ML, Y0 - G::MR);
+    uint32_t* bm = bms + (wave * G::BPW + b) * BMW;
+    for (int i = g; i < BMW; i += L) bm[i] = 0u;
     __syncthreads();
     if (exists) {
         Bounds bd;

@@ -25,9 +25,10 @@ __device__ __forceinline__ void stage_window(uint32_t* dst, const uint8_t* frame
             const int gx = xs + 4 * w, gy = ys + r;
             in[u] = gx >= 0 && gx < W && gy >= 0 && gy < H;
             const int cx = min(max(gx, 0), W - 4), cy = min(max(gy, 0), H - 1);
-            // In-frame offset: below 2^31 (height * pitch is), with a 24-bit
-            // row product (pitch < 2^24 then, as height >= 8).
-            v[u] = *reinterpret_cast<const uint32_t*>(frame + (uint32_t)(__mul24(cy, pitch) + cx));
+            // In-frame offset: below 2^31, as height * pitch is.  (A 24-bit
+            // product would not do: a frame of few rows may have a pitch of
+            // 2^23 bytes or more.)
+            v[u] = *reinterpret_cast<const uint32_t*>(frame + (uint32_t)(cy * pitch + cx));
             w += dw;
             r += dr;
             if (w >= words) {

@@ -164,6 +164,25 @@ def test_pitch_wider_than_frame():
     assert_same(me.fullsearch(tc, tr, 16, 7), oracle_pairs(oracle.fullsearch, cur[None], ref[None], 16, 7), "pitch fs")
 
 
+def test_pitch_of_2_23_bytes_and_more():
+    """Frames of few rows may have row pitches beyond 24-bit products (height *
+    pitch < 2^31 is the only limit): 16 rows at a pitch of 2^23 + 16 bytes."""
+    cur, ref = random_pair(16, 32, 16, 7, seed=12)
+    pitch = (1 << 23) + 16
+    big = torch.zeros((2, 16, pitch), dtype=torch.uint8, device=DEV)
+    big[0, :, :32], big[1, :, :32] = to_dev(cur), to_dev(ref)
+    tc, tr = big[0:1, :, :32], big[1:2, :, :32]
+    assert tc.stride(1) == pitch
+    for R in (7, 15):
+        say("case pitch 2^23 + 16, R=%d" % R)
+        assert_same(me.fullsearch(tc, tr, 16, R), oracle_pairs(oracle.fullsearch, cur[None], ref[None], 16, R),
+                    "wide pitch fs")
+        assert_same(me.dcds(tc, tr, 16, R), oracle_pairs(oracle.dcds, cur[None], ref[None], 16, R),
+                    "wide pitch dcds")
+    del big
+    torch.cuda.empty_cache()
+
+
 def test_zero_pairs_is_a_no_op():
     t = torch.zeros((0, 32, 32), dtype=torch.uint8, device=DEV)
     mv, sad, nsp = me.dcds(t, t, 16, 7)
@@ -297,7 +316,8 @@ CONFIGS8 = [(r, w) for r in (1, 2) for w in (1, 2, 4, 8)]
 @pytest.mark.parametrize("B,cfg", [(16, c) for c in CONFIGS16] + [(8, c) for c in CONFIGS8])
 def test_every_kernel_configuration(B, cfg, seq1080):
     """Each rows-per-lane x waves-per-group layout gives the oracle's results:
-    ragged small frames at every range class, and two 1920x1088 pairs."""
+    ragged small frames at every range class, with 16-byte and with 4-byte
+    loads (frames 4 bytes off a 16-byte boundary), and two 1920x1088 pairs."""
     try:
         for R in (3, 7, 8, 15, 16, 31):
             assert me.me_set_config(B, R, cfg) == me.ME_OK
@@ -308,6 +328,12 @@ def test_every_kernel_configuration(B, cfg, seq1080):
             assert_same(me.dcds(tc, tr, B, R, algo=me.ME_ALGO_DCDS_S),
                         oracle_pairs(oracle.dcds, cur[None], ref[None], B, R, variant=oracle.VARIANT_DCDS_S),
                         "cfg dcds_s")
+            say("case config", cfg, "B=%d R=%d ragged, 4-byte loads" % (B, R))
+            big = np.zeros((2, 1, 48, 96), np.uint8)
+            big[0, 0, :, 4:84], big[1, 0, :, 4:84] = cur, ref
+            tb = to_dev(big)
+            assert_same(me.dcds(tb[0, :, :, 4:84], tb[1, :, :, 4:84], B, R),
+                        oracle_pairs(oracle.dcds, cur[None], ref[None], B, R), "cfg dcds 4-byte loads")
         tseq = to_dev(seq1080[:3])
         say("case config", cfg, "B=%d 1080p" % B)
         assert_same(me.dcds(tseq[1:], tseq[:-1], B, 15),
