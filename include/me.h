@@ -232,7 +232,9 @@ int me_dcds_surface(const int32_t *cost, const uint8_t *valid, int32_t n, int32_
  * library's addition; the search itself is the one above).  A job is one
  * frame sequence (its own size, pitch and pair count; the block size and the
  * range are the batch's).  Each job's arguments follow me_search; start/orient
- * must be NULL for ME_ALGO_FS.  Up to 4096 jobs.
+ * must be NULL for ME_ALGO_FS.  Up to 4096 jobs and 2^30 work tiles (a
+ * tile is one block for FS and one workgroup's blocks, at most 128, for DCDS;
+ * ME_EUNSUPPORTED beyond).
  *
  * The host copies the job table into a pinned buffer; the device work is
  * {table copy, counter reset, persistent kernel}, captured once per kernel

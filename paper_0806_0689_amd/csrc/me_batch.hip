@@ -195,7 +195,10 @@ int batch_launch(const me_job* jobs, int32_t n_jobs, int32_t algo, int32_t block
         b.nsp = j.nsp;
         b.sse = j.sse;
         total += (long long)b.a.tiles_x * b.a.tiles_y * j.n_pairs;
-        if (total > INT32_MAX) return ME_EUNSUPPORTED;
+        // The shared tile counter runs past the total by kBatchChunk for every
+        // workgroup before each has seen the end: 2^30 keeps it far from
+        // int overflow.
+        if (total > (1 << 30)) return ME_EUNSUPPORTED;
         tab.push_back(b);
     }
     if (tab.empty()) return ME_OK;

@@ -191,6 +191,10 @@ def test_batch_argument_checks():
     assert me.me_batch(bad, 1, me.ME_ALGO_FS, 16, 7) == me.ME_EINVAL
     empty = (J * 1)(J(None, None, 64, 32, 64, 0, 0, None, None, None, None, None))  # zero pairs
     assert me.me_batch(empty, 1, me.ME_ALGO_DCDS, 16, 7) == me.ME_OK
+    # More than 2^30 work tiles in one call (FS: one tile per block), rejected
+    # before any device work: 1024 blocks per pair, 2^20 + 1 pairs.
+    huge = (J * 1)(J(P, P, 16384, 16, 16384, (1 << 20) + 1, 16 * 16384, P, P, P, None, None))
+    assert me.me_batch(huge, 1, me.ME_ALGO_FS, 16, 7) == me.ME_EUNSUPPORTED
 
 
 def test_autotune_argument_checks(tmp_path):
