@@ -103,7 +103,7 @@ int launch_dcds_cfg(const uint8_t* cur, const uint8_t* ref, int32_t width, int32
                     const uint8_t* orient, me_mv* mv, uint32_t* sad, uint32_t* nsp, uint32_t* sse,
                     hipStream_t st) {
     using G = DcdsGeo<B, RPL, WPG, RMAX>;
-    const size_t lds = dcds_lds_bytes<B, RPL, WPG, RMAX>(range);
+    const size_t lds = dcds_lds_bytes<B, RPL, WPG, RMAX>();
     if (lds > kMaxLds) return ME_EUNSUPPORTED;
     if (lds > 65536) {
         // Windows above 64 KiB need the kernel's dynamic-LDS limit raised once.
@@ -334,8 +334,8 @@ ME_EXPORT int me_dcds_surface(const int32_t* cost, const uint8_t* valid, int32_t
     if (orient && !start) return ME_EINVAL;
     if (n == 0) return ME_OK;
     if (!cost || !mv || !cost_out || !nsp) return ME_EINVAL;
-    const size_t lds = (size_t)4 * 16 * bitmap_words(range);
-    const unsigned grid = (unsigned)((n + 15) / 16);
+    const size_t lds = (size_t)4 * (16 * bitmap_words(31) + bitmap_slack(16, 31));
+    const unsigned grid = (unsigned)(((int64_t)n + 15) / 16);
     hipLaunchKernelGGL(k_dcds_surface, dim3(grid), dim3(256), lds, reinterpret_cast<hipStream_t>(stream), cost, valid,
                        n, range, algo == ME_ALGO_DCDS_S, reinterpret_cast<const int16_t*>(start), orient,
                        reinterpret_cast<int16_t*>(mv), cost_out, nsp);

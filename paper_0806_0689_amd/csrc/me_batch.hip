@@ -106,26 +106,26 @@ struct Variant {
 };
 
 template <int B, int RPL, int WPG, int RMAX>
-Variant dcds_variant(int R) {
+Variant dcds_variant() {
     return Variant{reinterpret_cast<const void*>(&k_dcds_batch<B, RPL, WPG, RMAX>), 64 * WPG,
-                   dcds_lds_bytes<B, RPL, WPG, RMAX>(R) + 16};
+                   dcds_lds_bytes<B, RPL, WPG, RMAX>() + 16};
 }
 
 template <int B, int RPL, int RMAX>
-Variant dcds_variant_w(int wpg, int R) {
-    if (wpg == 1) return dcds_variant<B, RPL, 1, RMAX>(R);
-    if (wpg == 2) return dcds_variant<B, RPL, 2, RMAX>(R);
-    if (wpg == 4) return dcds_variant<B, RPL, 4, RMAX>(R);
-    return dcds_variant<B, RPL, 8, RMAX>(R);
+Variant dcds_variant_w(int wpg) {
+    if (wpg == 1) return dcds_variant<B, RPL, 1, RMAX>();
+    if (wpg == 2) return dcds_variant<B, RPL, 2, RMAX>();
+    if (wpg == 4) return dcds_variant<B, RPL, 4, RMAX>();
+    return dcds_variant<B, RPL, 8, RMAX>();
 }
 
 template <int B, int RMAX>
-Variant dcds_variant_r(int rpl, int wpg, int R) {
-    if (rpl == 1) return dcds_variant_w<B, 1, RMAX>(wpg, R);
+Variant dcds_variant_r(int rpl, int wpg) {
+    if (rpl == 1) return dcds_variant_w<B, 1, RMAX>(wpg);
     if constexpr (B == 16) {
-        if (rpl == 4) return dcds_variant_w<B, 4, RMAX>(wpg, R);
+        if (rpl == 4) return dcds_variant_w<B, 4, RMAX>(wpg);
     }
-    return dcds_variant_w<B, 2, RMAX>(wpg, R);
+    return dcds_variant_w<B, 2, RMAX>(wpg);
 }
 
 Variant pick_variant(int kind, int B, int rpl, int wpg, int R) {
@@ -140,13 +140,13 @@ Variant pick_variant(int kind, int B, int rpl, int wpg, int R) {
     }
     const int rc = range_class(R);
     if (B == 16) {
-        if (rc == 0) return dcds_variant_r<16, 7>(rpl, wpg, R);
-        if (rc == 1) return dcds_variant_r<16, 15>(rpl, wpg, R);
-        return dcds_variant_r<16, 31>(rpl, wpg, R);
+        if (rc == 0) return dcds_variant_r<16, 7>(rpl, wpg);
+        if (rc == 1) return dcds_variant_r<16, 15>(rpl, wpg);
+        return dcds_variant_r<16, 31>(rpl, wpg);
     }
-    if (rc == 0) return dcds_variant_r<8, 7>(rpl, wpg, R);
-    if (rc == 1) return dcds_variant_r<8, 15>(rpl, wpg, R);
-    return dcds_variant_r<8, 31>(rpl, wpg, R);
+    if (rc == 0) return dcds_variant_r<8, 7>(rpl, wpg);
+    if (rc == 1) return dcds_variant_r<8, 15>(rpl, wpg);
+    return dcds_variant_r<8, 31>(rpl, wpg);
 }
 
 // Enqueues copy + reset + persistent kernel on `st` (capturing or not).

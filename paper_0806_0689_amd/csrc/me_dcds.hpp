@@ -56,12 +56,12 @@ struct DcdsGeo {
     static_assert(L >= 2 && BPW * L == 64, "lanes per block must divide the wave");
 };
 
-__host__ __device__ constexpr int bitmap_words(int R) { return ((2 * R + 1) * (2 * R + 1) + 31) / 32; }
-
+// LDS of one workgroup: the window, then one bitmap per block, each sized
+// for the range class, and the bitmaps' slack.
 template <int B, int RPL, int WPG, int RMAX>
-__host__ __device__ constexpr size_t dcds_lds_bytes(int R) {
+__host__ __device__ constexpr size_t dcds_lds_bytes() {
     using G = DcdsGeo<B, RPL, WPG, RMAX>;
-    return (size_t)4 * (G::WIN_WORDS + G::BPW * WPG * bitmap_words(R));
+    return (size_t)4 * (G::WIN_WORDS + G::BPW * WPG * bitmap_words(RMAX) + bitmap_slack(G::L, RMAX));
 }
 
 // Stages column c (CH bytes at window x offset c * CH) of the window rows
@@ -284,8 +284,8 @@ __device__ __forceinline__ void dcds_tile(uint32_t* smem, const FrameArgs& a, in
                                           uint32_t* __restrict__ nsp, uint32_t* __restrict__ sse) {
     using G = DcdsGeo<B, RPL, WPG, RMAX>;
     constexpr int L = G::L, K = G::K;
+    constexpr int BMW = bitmap_words(RMAX);
     const int R = a.R;
-    const int BMW = bitmap_words(R);
     uint32_t* win = smem;
     uint32_t* bms = smem + G::WIN_WORDS;
     const uint8_t* curf = a.cur + (long long)pair * a.pair_stride;
@@ -337,8 +337,15 @@ __device__ __forceinline__ void dcds_tile(uint32_t* smem, const FrameArgs& a, in
         stage<G::NEED * 4, G::WDW, G::WR, 64 * WPG, true>(win, reff, a.W, a.H, a.pitch, X0 - G::ML, Y0 - G::MR);
     else
         stage<G::NEED * 4, G::WDW, G::WR, 64 * WPG, false>(win, reff, a.W, a.H, a.pitch, X0 - G::ML, Y0 - G::MR);
+    // Every bitmap of the tile starts empty: the workgroup clears them
+    // together.
+    {
+        constexpr int NT = 64 * WPG, N = G::BPW * WPG * BMW;
+#pragma unroll
+        for (int j = 0; j < (N + NT - 1) / NT; ++j)
+            if ((j + 1) * NT <= N || (int)threadIdx.x + j * NT < N) bms[threadIdx.x + j * NT] = 0u;
+    }
     uint32_t* bm = bms + (wave * G::BPW + b) * BMW;
-    for (int i = g; i < BMW; i += L) bm[i] = 0u;
     __syncthreads();
     if (exists) {
         Bounds bd;

@@ -52,6 +52,16 @@ struct Room {
     __device__ __forceinline__ int pp(bool t) const { return t ? xh : yh; }
 };
 
+// The visited-point bitmap of one search: one bit per window point,
+// (2R + 1)^2 bits, in bitmap_words(RMAX) words.  To count, each of the L
+// lanes reads the same number of words; the last read of some lanes lies
+// past the bitmap (and is ignored), so an array of bitmaps is followed by
+// bitmap_slack(L, RMAX) more words.
+__host__ __device__ constexpr int bitmap_words(int R) { return ((2 * R + 1) * (2 * R + 1) + 31) / 32; }
+__host__ __device__ constexpr int bitmap_slack(int L, int RMAX) {
+    return (bitmap_words(RMAX) + L - 1) / L * L - bitmap_words(RMAX);
+}
+
 __device__ __forceinline__ uint32_t key(bool valid, uint32_t cost, uint32_t idx) {
     return valid ? ((cost << 3) | idx) : 0xFFFFFFFFu;
 }
@@ -66,6 +76,7 @@ __device__ __forceinline__ uint32_t key(bool valid, uint32_t cost, uint32_t idx)
 // Points outside the candidate set may be evaluated on any finite data; their
 // results are masked here.
 // SIMPLIFIED: Step 4 of DCDS^S; SEEDED: learned start (sx, sy, orient_v).
+// bm: the group's bitmap, bitmap_words(RMAX) words, all zero on entry.
 template <int L, int RMAX, bool SIMPLIFIED, bool SEEDED, class Ev>
 __device__ SearchOut dcds_search(const Ev& ev, int R, const Bounds& bd, uint32_t* bm, int g, int sx, int sy,
                                  bool orient_v) {
@@ -80,16 +91,16 @@ __device__ SearchOut dcds_search(const Ev& ev, int R, const Bounds& bd, uint32_t
         if (act) (void)atomicOr(&bm[k >> 5], 1u << (k & 31));
     };
     // NSP: the number of bits set (the group's own LDS operations complete in
-    // order, so every mark is visible here).  RMAX bounds R, so the word loop
-    // has a fixed trip count.
+    // order, so every mark is visible here).  Words past the window's bits
+    // are zero; every lane reads NW words, and a last word beyond the bitmap
+    // is dropped.
     auto count = [&]() -> uint32_t {
-        constexpr int WMAX = ((2 * RMAX + 1) * (2 * RMAX + 1) + 31) / 32;
-        const int words = (S * S + 31) / 32;
+        constexpr int WMAX = bitmap_words(RMAX), NW = (WMAX + L - 1) / L;
         uint32_t n = 0;
 #pragma unroll
-        for (int j = 0; j < (WMAX + L - 1) / L; ++j) {
-            const int i = g + j * L;
-            if (i < words) n += __popc(bm[i]);
+        for (int j = 0; j < NW; ++j) {
+            const uint32_t w = bm[g + j * L];
+            n += __popc(j < NW - 1 || g + j * L < WMAX ? w : 0u);
         }
         return group_sum<L>(n);
     };

@@ -40,8 +40,8 @@ __global__ __launch_bounds__(256) void k_dcds_surface(const int32_t* __restrict_
                                                       const uint8_t* __restrict__ orient, int16_t* __restrict__ mv,
                                                       uint32_t* __restrict__ out_cost, uint32_t* __restrict__ nsp) {
     constexpr int L = 16;
+    constexpr int BMW = bitmap_words(31);
     extern __shared__ uint32_t smem[];
-    const int BMW = bitmap_words(R);
     const int gi = threadIdx.x / L, g = threadIdx.x % L;
     const long long s = (long long)blockIdx.x * (256 / L) + gi;
     uint32_t* bm = smem + gi * BMW;
