@@ -67,20 +67,20 @@ __host__ __device__ constexpr size_t dcds_lds_bytes() {
 // Stages column c (CH bytes at window x offset c * CH) of the window rows
 // r0, r0 + RS, ... (NP of them) into LDS.  Only the last of them can reach
 // past the window; it is replaced by row WR - 1, which then gets the same
-// chunk from two threads (so no store is conditional).  The
-// window's x origin xs and W are multiples of CH, so a chunk lies wholly
-// inside or outside the frame; chunks outside read as 0 (no valid candidate
-// uses them).  Every load reads a clamped in-frame address, at a 32-bit
-// offset (a frame spans less than 2^31 bytes), and up to four loads are in
-// flight before the first store.
+// chunk from two threads (so no store is conditional).  The window's x
+// origin xs and W are multiples of CH, so a chunk lies wholly inside or
+// outside the frame.  Every load reads a clamped in-frame address, at a
+// 32-bit offset (a frame spans less than 2^31 bytes), so a chunk outside the
+// frame holds a copy of frame pixels: no valid candidate reads it, and the
+// searches mask every point they evaluate outside the candidate set, which
+// only needs finite data there.  Up to four loads are in flight before the
+// first store.
 template <int CH, int WDW, int WR, int RS, int NP>
 __device__ __forceinline__ void stage_column(uint32_t* win, const uint8_t* frame, int W, int H, int pitch, int xs,
                                              int ys, int c, int r0) {
     constexpr int CW = CH / 4;  // words per chunk
     constexpr int U = 4;        // loads per batch
-    const int gx = xs + c * CH;
-    const bool xin = gx >= 0 && gx < W;
-    const int cx = min(max(gx, 0), W - CH);
+    const int cx = min(max(xs + c * CH, 0), W - CH);
     for (int p0 = 0; p0 < NP; p0 += U) {
         uint32_t v[U][CW];
         int r[U];
@@ -104,12 +104,10 @@ __device__ __forceinline__ void stage_column(uint32_t* win, const uint8_t* frame
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int gy = ys + r[u];
-            const bool in = xin && gy >= 0 && gy < H;
             if (p0 + u < NP) {
                 uint32_t* dst = win + r[u] * WDW + c * CW;
 #pragma unroll
-                for (int k = 0; k < CW; ++k) dst[k] = in ? v[u][k] : 0u;
+                for (int k = 0; k < CW; ++k) dst[k] = v[u][k];
             }
         }
     }

@@ -160,7 +160,9 @@ __device__ SearchOut dcds_search(const Ev& ev, int R, const Bounds& bd, uint32_t
     int dir;
     uint32_t kcost = 0;  // cost of the distant point behind the centre
     {
-        const int o = w == 1 ? -1 : w == 2 ? 1 : w == 3 ? -2 : w == 4 ? 2 : w == 5 ? -1 : 1;
+        // Offset of cross point w (1..6) along its axis, from a table of
+        // 4-bit fields holding o + 2: -1, +1, -2, +2, -1, +1.
+        const int o = (int)((0x3140310u >> (w << 2)) & 15u) - 2;
         const bool along_x = (w <= 4) != t;
         if (along_x) cx += o; else cy += o;
         t = !along_x;
