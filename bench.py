@@ -39,8 +39,21 @@ def src_digest() -> str:
     return h.hexdigest()[:16]
 
 
+# Before the warmup launches of each timed loop, the launch is repeated for
+# this long: an idle GPU starts at lower clocks, and a handful of
+# sub-millisecond launches does not bring it to its steady state (measured:
+# the headline launch reads about 10% slower after 5 warmup launches alone).
+SETTLE_MS = 200.0
+
+
 def time_launches(fn, steps, warmup, torch):
-    """Per-launch durations (ms) from HIP events on the launch stream."""
+    """Per-launch durations (ms) from HIP events on the launch stream, after
+    SETTLE_MS of untimed repeats and `warmup` untimed launches."""
+    t_end = time.perf_counter() + SETTLE_MS * 1e-3
+    while time.perf_counter() < t_end:
+        for _ in range(8):
+            fn()
+        torch.cuda.synchronize()
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -304,6 +317,7 @@ def config5_leg(me, torch, dev, args):
 
 
 def main():
+    global SETTLE_MS
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
@@ -315,9 +329,12 @@ def main():
     ap.add_argument("--sweep", action="store_true",
                     help="time every DCDS kernel configuration (rows per lane x waves per group) and exit")
     ap.add_argument("--sweep-range", type=int, default=RANGE, help="search range of --sweep")
+    ap.add_argument("--settle-ms", type=float, default=SETTLE_MS,
+                    help="untimed repeats of each timed launch before its warmup, in ms (0: none)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy 256 MiB device-to-device (a known-size kernel for counter calibration)")
     args = ap.parse_args()
+    SETTLE_MS = args.settle_ms
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path "
               "(blocks are independent; sharding across GPUs needs no exchange).", file=sys.stderr)
@@ -443,6 +460,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "settle_ms": SETTLE_MS,
         "ms_per_step": d["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
