@@ -35,7 +35,9 @@
  *   - Sequences: a call covers `n_pairs` frame pairs; pair p reads
  *     cur + p * pair_stride and ref + p * pair_stride (bytes).  For a sequence
  *     stored as frames [T][height][pitch], pass cur = frame 1, ref = frame 0,
- *     pair_stride = height * pitch and n_pairs = T - 1.
+ *     pair_stride = height * pitch and n_pairs = T - 1.  A call over more
+ *     pairs than one kernel launch holds (2^31 - 1 work-items) is issued as
+ *     several launches over consecutive pair ranges, in order on `stream`.
  *   - Outputs are device arrays of n_pairs * (height/block) * (width/block)
  *     entries in pair-major, then raster block order, owned by the caller.
  *   - Calls are asynchronous and ordered on `stream` (a hipStream_t; NULL is
@@ -310,7 +312,9 @@ int me_proposer_get_grads(me_proposer *p, float *host, int32_t n);          /* l
 /* Adam moments (host, flat layout) and step count, for checkpoints.        */
 int me_proposer_get_state(me_proposer *p, float *m, float *v, int64_t *step, int32_t n);
 int me_proposer_set_state(me_proposer *p, const float *m, const float *v, int64_t step, int32_t n);
-/* head: device fp32 [n_pairs][height/16][width/16][3].                      */
+/* head: device fp32 [n_pairs][height/16][width/16][3].  forward and
+ * train_step take at most 65535 pairs and height/4 <= 65535 per call
+ * (ME_EUNSUPPORTED beyond).                                                */
 int me_proposer_forward(me_proposer *p, const uint8_t *cur, const uint8_t *ref, int32_t width, int32_t height,
                         int32_t pitch, int64_t pair_stride, int32_t n_pairs, float *head, void *stream);
 /* Parameter gradients (me_proposer_get_grads) for a head gradient of the

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <atomic>
 
 #include "me.h"
@@ -55,6 +56,13 @@ FrameArgs frame_args(const uint8_t* cur, const uint8_t* ref, int32_t width, int3
 }
 
 int launched() { return hipGetLastError() == hipSuccess ? ME_OK : ME_EDEVICE; }
+
+// A dispatch counts its work-items in 32 bits, so one launch stays below 2^31
+// of them: a call over more pairs is split into launches over consecutive
+// pair ranges, each with its pointers offset to its first pair.
+int pairs_per_launch(long long items_per_pair) {
+    return (int)std::max<long long>(1, std::min<long long>(INT32_MAX, (long long)INT32_MAX / items_per_pair));
+}
 
 // ---------------------------------------------------------------------------
 // DCDS kernel configurations: rows per lane x waves per workgroup, per block
@@ -115,12 +123,23 @@ int launch_dcds_cfg(const uint8_t* cur, const uint8_t* ref, int32_t width, int32
             raised.store(1);
         }
     }
-    const FrameArgs a = frame_args(cur, ref, width, height, pitch, pair_stride, B, range, G::BPW, WPG);
-    const long long grid = (long long)a.tiles_x * a.tiles_y * n_pairs;
-    if (grid > INT32_MAX) return ME_EUNSUPPORTED;
-    hipLaunchKernelGGL((k_dcds<B, RPL, WPG, RMAX>), dim3((unsigned)grid), dim3(64 * WPG), lds, st, a, flags,
-                       reinterpret_cast<const int16_t*>(start), orient, reinterpret_cast<int16_t*>(mv), sad, nsp, sse);
-    return launched();
+    const FrameArgs a0 = frame_args(cur, ref, width, height, pitch, pair_stride, B, range, G::BPW, WPG);
+    const long long tiles = (long long)a0.tiles_x * a0.tiles_y, blocks = (long long)a0.bw * a0.bh;
+    const int ppl = pairs_per_launch(tiles * 64 * WPG);
+    for (int p0 = 0; p0 < n_pairs; p0 += ppl) {
+        const int np = std::min(ppl, n_pairs - p0);
+        const long long o = p0 * blocks;
+        FrameArgs a = a0;
+        a.cur = cur + p0 * pair_stride;
+        a.ref = ref + p0 * pair_stride;
+        hipLaunchKernelGGL((k_dcds<B, RPL, WPG, RMAX>), dim3((unsigned)(tiles * np)), dim3(64 * WPG), lds, st, a,
+                           flags, start ? reinterpret_cast<const int16_t*>(start + o) : nullptr,
+                           orient ? orient + o : nullptr, reinterpret_cast<int16_t*>(mv + o), sad + o, nsp + o,
+                           sse ? sse + o : nullptr);
+        const int rc = launched();
+        if (rc != ME_OK) return rc;
+    }
+    return ME_OK;
 }
 
 template <int B, int RPL, int RMAX>
@@ -211,27 +230,29 @@ ME_EXPORT int me_search(const uint8_t* cur, const uint8_t* ref, int32_t width, i
     if (n_pairs == 0) return ME_OK;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (algo == ME_ALGO_FS) {
-        const FrameArgs a = frame_args(cur, ref, width, height, pitch, pair_stride, block, range, 1, 1);
-        const long long grid = (long long)a.bw * a.bh * n_pairs;
+        const FrameArgs a0 = frame_args(cur, ref, width, height, pitch, pair_stride, block, range, 1, 1);
+        const long long blocks = (long long)a0.bw * a0.bh;
         const int nt = fs_threads(range);
         const bool split = fs_split(range);
-        int16_t* mvp = reinterpret_cast<int16_t*>(mv);
-        if (block == 16) {
-            if (split)
-                hipLaunchKernelGGL((k_fs<16, true>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<16>(range), st, a,
-                                   mvp, sad, nsp, sse);
-            else
-                hipLaunchKernelGGL((k_fs<16, false>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<16>(range), st, a,
-                                   mvp, sad, nsp, sse);
-        } else {
-            if (split)
-                hipLaunchKernelGGL((k_fs<8, true>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<8>(range), st, a,
-                                   mvp, sad, nsp, sse);
-            else
-                hipLaunchKernelGGL((k_fs<8, false>), dim3((unsigned)grid), dim3(nt), fs_lds_bytes<8>(range), st, a,
-                                   mvp, sad, nsp, sse);
+        const size_t lds = block == 16 ? fs_lds_bytes<16>(range) : fs_lds_bytes<8>(range);
+        const void* fn = block == 16 ? (split ? reinterpret_cast<const void*>(&k_fs<16, true>)
+                                              : reinterpret_cast<const void*>(&k_fs<16, false>))
+                                     : (split ? reinterpret_cast<const void*>(&k_fs<8, true>)
+                                              : reinterpret_cast<const void*>(&k_fs<8, false>));
+        const int ppl = pairs_per_launch(blocks * nt);
+        for (int p0 = 0; p0 < n_pairs; p0 += ppl) {
+            const int np = std::min(ppl, n_pairs - p0);
+            const long long o = p0 * blocks;
+            FrameArgs a = a0;
+            a.cur = cur + p0 * pair_stride;
+            a.ref = ref + p0 * pair_stride;
+            int16_t* mvp = reinterpret_cast<int16_t*>(mv + o);
+            uint32_t *sadp = sad + o, *nspp = nsp + o, *ssep = sse ? sse + o : nullptr;
+            void* args[] = {&a, &mvp, &sadp, &nspp, &ssep};
+            if (hipLaunchKernel(fn, dim3((unsigned)(blocks * np)), dim3(nt), args, lds, st) != hipSuccess)
+                return ME_EDEVICE;
         }
-        return launched();
+        return ME_OK;
     }
     const int flags = dcds_flags(algo, cur, ref, width, pitch, pair_stride);
     int rpl, wpg;
@@ -274,10 +295,18 @@ ME_EXPORT int me_frame_quality(const me_mv* mv, const uint32_t* sad, const uint3
     if (!aligned(out, 8)) return ME_EINVAL;
     const long long nb = (long long)(width / block) * (height / block);
     if (nb * n_pairs > (long long)INT32_MAX) return ME_EUNSUPPORTED;
-    hipLaunchKernelGGL(k_frame_quality, dim3((unsigned)n_pairs), dim3(256), 0, reinterpret_cast<hipStream_t>(stream),
-                       reinterpret_cast<const int16_t*>(mv), sad, sse, reinterpret_cast<const int16_t*>(mv_true),
-                       (int)nb, block, reinterpret_cast<QualityOut*>(out));
-    return launched();
+    const int ppl = pairs_per_launch(256);
+    for (int p0 = 0; p0 < n_pairs; p0 += ppl) {
+        const int np = std::min(ppl, n_pairs - p0);
+        const long long o = p0 * nb;
+        hipLaunchKernelGGL(k_frame_quality, dim3((unsigned)np), dim3(256), 0, reinterpret_cast<hipStream_t>(stream),
+                           reinterpret_cast<const int16_t*>(mv + o), sad + o, sse + o,
+                           mv_true ? reinterpret_cast<const int16_t*>(mv_true + o) : nullptr, (int)nb, block,
+                           reinterpret_cast<QualityOut*>(out) + p0);
+        const int rc = launched();
+        if (rc != ME_OK) return rc;
+    }
+    return ME_OK;
 }
 
 ME_EXPORT int me_mvp_stats(const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t height, int32_t pitch,
@@ -335,9 +364,17 @@ ME_EXPORT int me_dcds_surface(const int32_t* cost, const uint8_t* valid, int32_t
     if (n == 0) return ME_OK;
     if (!cost || !mv || !cost_out || !nsp) return ME_EINVAL;
     const size_t lds = (size_t)4 * (16 * bitmap_words(31) + bitmap_slack(16, 31));
-    const unsigned grid = (unsigned)(((int64_t)n + 15) / 16);
-    hipLaunchKernelGGL(k_dcds_surface, dim3(grid), dim3(256), lds, reinterpret_cast<hipStream_t>(stream), cost, valid,
-                       n, range, algo == ME_ALGO_DCDS_S, reinterpret_cast<const int16_t*>(start), orient,
-                       reinterpret_cast<int16_t*>(mv), cost_out, nsp);
-    return launched();
+    const long long side2 = (long long)(2 * range + 1) * (2 * range + 1);
+    const int per = pairs_per_launch(16) / 16 * 16;  // surfaces per launch, whole workgroups
+    for (int s0 = 0; s0 < n; s0 += per) {
+        const int ns = std::min(per, n - s0);
+        hipLaunchKernelGGL(k_dcds_surface, dim3((unsigned)((ns + 15) / 16)), dim3(256), lds,
+                           reinterpret_cast<hipStream_t>(stream), cost + s0 * side2, valid ? valid + s0 * side2 : nullptr,
+                           ns, range, algo == ME_ALGO_DCDS_S,
+                           start ? reinterpret_cast<const int16_t*>(start + s0) : nullptr, orient ? orient + s0 : nullptr,
+                           reinterpret_cast<int16_t*>(mv + s0), cost_out + s0, nsp + s0);
+        const int rc = launched();
+        if (rc != ME_OK) return rc;
+    }
+    return ME_OK;
 }

@@ -196,3 +196,18 @@ def test_set_weights_rejects_non_finite():
     w[5] = np.nan
     with pytest.raises(me.MEError):
         p.set_weights(w)
+
+
+def test_forward_grid_limits():
+    """forward and train_step put rows and pairs on grid dimensions y and z:
+    more than 65535 pairs, or height/4 above 65535, is refused before any
+    device work (the frame pointers here are never read)."""
+    p = me.Proposer()
+    fake = 0x1000
+    L = me.lib()
+    # 65536 pairs of 16x16 frames.
+    assert L.me_proposer_forward(p.h, fake, fake, 16, 16, 16, 256, 65536, fake, None) == me.ME_EUNSUPPORTED
+    # One 16x262160 frame: height/4 = 65540.
+    assert L.me_proposer_forward(p.h, fake, fake, 16, 262160, 16, 16 * 262160, 1, fake, None) == me.ME_EUNSUPPORTED
+    assert L.me_proposer_train_step(p.h, fake, fake, 16, 16, 16, 256, 65536, fake, 0.001, fake,
+                                    None) == me.ME_EUNSUPPORTED
