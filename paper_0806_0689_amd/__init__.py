@@ -301,10 +301,31 @@ def _frames(cur, ref):
     return P, H, W, cur.stride(-2), stride
 
 
+def _arg(t, n, dtype, device, name):
+    """A caller tensor that a kernel reads or writes by block index: it must
+    live on the frames' device with the given dtype, be contiguous and hold
+    exactly n elements, or the kernel would run past it."""
+    if t is None:
+        return None
+    if t.device != device or t.dtype != dtype or not t.is_contiguous() or t.numel() != n:
+        raise ValueError("%s must be a contiguous %s tensor of %d elements on %s (got %s, %d elements, %s%s)" % (
+            name, dtype, n, device, t.dtype, t.numel(), t.device, "" if t.is_contiguous() else ", not contiguous"))
+    return t
+
+
+def _block_args(P, hb, wb, device, start=None, orient=None):
+    torch = _torch()
+    n = P * hb * wb
+    return (_arg(start, 2 * n, torch.int16, device, "start"), _arg(orient, n, torch.uint8, device, "orient"))
+
+
 def _outputs(P, hb, wb, device, out):
     torch = _torch()
     if out is not None:
-        return out
+        mv, sad, nsp = out
+        n = P * hb * wb
+        return (_arg(mv, 2 * n, torch.int16, device, "mv"), _arg(sad, n, torch.int32, device, "sad"),
+                _arg(nsp, n, torch.int32, device, "nsp"))
     mv = torch.empty((P, hb, wb, 2), dtype=torch.int16, device=device)
     sad = torch.empty((P, hb, wb), dtype=torch.int32, device=device)
     nsp = torch.empty((P, hb, wb), dtype=torch.int32, device=device)
@@ -337,6 +358,7 @@ def dcds(cur, ref, block=16, range_=7, algo=ME_ALGO_DCDS, start=None, orient=Non
     vectors (int16 [P, H/B, W/B, 2]) and first-cross orientations (uint8)."""
     P, H, W, pitch, stride = _frames(cur, ref)
     mv, sad, nsp = _outputs(P, H // block, W // block, cur.device, out)
+    start, orient = _block_args(P, H // block, W // block, cur.device, start, orient)
     sp = start.data_ptr() if start is not None else None
     op = orient.data_ptr() if orient is not None else None
     rc = me_dcds_ex(cur.data_ptr(), ref.data_ptr(), W, H, pitch, stride, P, block, range_, algo, sp, op,
@@ -353,9 +375,11 @@ def search(cur, ref, block=16, range_=7, algo=ME_ALGO_DCDS, start=None, orient=N
     torch = _torch()
     P, H, W, pitch, stride = _frames(cur, ref)
     mv, sad, nsp = _outputs(P, H // block, W // block, cur.device, out[:3] if out is not None else None)
+    start, orient = _block_args(P, H // block, W // block, cur.device, start, orient)
     e = None
     if sse:
         e = out[3] if out is not None and len(out) > 3 else torch.empty_like(sad)
+        e = _arg(e, sad.numel(), torch.int32, cur.device, "sse")
     sp = start.data_ptr() if start is not None else None
     op = orient.data_ptr() if orient is not None else None
     rc = me_search(cur.data_ptr(), ref.data_ptr(), W, H, pitch, stride, P, block, range_, algo, sp, op,
@@ -376,15 +400,27 @@ def frame_quality(mv, sad, sse, mv_true=None, block=16, stream=None):
         mv, sad, sse = mv[None], sad[None], sse[None]
         mv_true = mv_true[None] if mv_true is not None else None
     P, hb, wb = mv.shape[:3]
-    for t in (mv, sad, sse) + ((mv_true,) if mv_true is not None else ()):
-        if not t.is_cuda or not t.is_contiguous():
-            raise ValueError("quality inputs must be contiguous GPU tensors")
+    n = P * hb * wb
+    if not mv.is_cuda:
+        raise ValueError("quality inputs must be GPU tensors")
+    _arg(mv, 2 * n, torch.int16, mv.device, "mv")
+    _arg(sad, n, torch.int32, mv.device, "sad")
+    _arg(sse, n, torch.int32, mv.device, "sse")
+    _arg(mv_true, 2 * n, torch.int16, mv.device, "mv_true")
     out = torch.empty(max(1, P) * QUALITY_BYTES, dtype=torch.uint8, device=mv.device)
     rc = me_frame_quality(mv.data_ptr(), sad.data_ptr(), sse.data_ptr(),
                           mv_true.data_ptr() if mv_true is not None else None, wb * block, hb * block, P, block,
                           out.data_ptr(), _stream(stream))
     _check(rc, "me_frame_quality")
     return out[:P * QUALITY_BYTES].cpu().numpy().view(np.dtype(QUALITY_FIELDS))
+
+
+def _mvp_counts(counts, range_, device):
+    torch = _torch()
+    hist, d1, d2 = counts
+    n = 2 * range_ + 1
+    return (_arg(hist, n * n, torch.int32, device, "hist"), _arg(d1, 9 * n * n, torch.int32, device, "d1"),
+            _arg(d2, 25 * n * n, torch.int32, device, "d2"))
 
 
 def mvp_stats(cur, ref, block=16, range_=7, counts=None, stream=None):
@@ -398,7 +434,7 @@ def mvp_stats(cur, ref, block=16, range_=7, counts=None, stream=None):
         counts = (torch.zeros(n * n, dtype=torch.int32, device=cur.device),
                   torch.zeros((9, n * n), dtype=torch.int32, device=cur.device),
                   torch.zeros((n * n, 25), dtype=torch.int32, device=cur.device))
-    hist, d1, d2 = counts
+    hist, d1, d2 = _mvp_counts(counts, range_, cur.device)
     rc = me_mvp_stats(cur.data_ptr(), ref.data_ptr(), W, H, pitch, stride, P, block, range_, hist.data_ptr(),
                       d1.data_ptr(), d2.data_ptr(), _stream(stream))
     _check(rc, "me_mvp_stats")
@@ -410,10 +446,10 @@ def mvp_tables(counts, range_, stream=None):
     quarter [R+1, R+1], ax, ay, bx, by [2R+1], regions [5], eta [5],
     d1 [9, 2R+1, 2R+1], d2 [2R+1, 2R+1, 5, 5], t1, t2 [5, 5]."""
     torch = _torch()
-    hist, d1, d2 = counts
     size = me_mvp_tables_size(range_)
     if size < 0:
         raise MEError(size, "me_mvp_tables_size")
+    hist, d1, d2 = _mvp_counts(counts, range_, counts[0].device)
     out = torch.empty(size, dtype=torch.float64, device=hist.device)
     _check(me_mvp_tables(hist.data_ptr(), d1.data_ptr(), d2.data_ptr(), range_, out.data_ptr(), _stream(stream)),
            "me_mvp_tables")
@@ -441,11 +477,11 @@ def make_jobs(pairs, block, starts=None, orients=None, outs=None, sses=None):
     outputs = []
     for i, (cur, ref) in enumerate(pairs):
         P, H, W, pitch, stride = _frames(cur, ref)
-        o = outs[i] if outs is not None else _outputs(P, H // block, W // block, cur.device, None)
+        o = _outputs(P, H // block, W // block, cur.device, outs[i] if outs is not None else None)
         mv, sad, nsp = o
-        st = starts[i] if starts is not None else None
-        orr = orients[i] if orients is not None else None
-        e = sses[i] if sses is not None else None
+        st, orr = _block_args(P, H // block, W // block, cur.device, starts[i] if starts is not None else None,
+                              orients[i] if orients is not None else None)
+        e = _arg(sses[i], sad.numel(), sad.dtype, cur.device, "sse") if sses is not None else None
         jobs[i] = MeJob(cur.data_ptr(), ref.data_ptr(), W, H, pitch, P, stride, mv.data_ptr(), sad.data_ptr(),
                         nsp.data_ptr(), st.data_ptr() if st is not None else None,
                         orr.data_ptr() if orr is not None else None, e.data_ptr() if e is not None else None)
@@ -534,10 +570,16 @@ class Proposer:
         rc = lib().me_proposer_forward(self.h, cur.data_ptr(), ref.data_ptr(), W, H, pitch, stride, P,
                                        head.data_ptr(), _stream(stream))
         _check(rc, "me_proposer_forward")
+        self._last = (head.numel(), cur.device)
         return head
 
     def backward(self, dhead, stream=None):
-        dhead = dhead.contiguous()
+        """Gradients for a head gradient shaped as the last forward's head."""
+        torch = _torch()
+        last = getattr(self, "_last", None)
+        if last is None:
+            raise MEError(ME_EINVAL, "me_proposer_backward (no forward yet)")
+        dhead = _arg(dhead.contiguous(), last[0], torch.float32, last[1], "dhead")
         _check(lib().me_proposer_backward(self.h, dhead.data_ptr(), _stream(stream)), "me_proposer_backward")
 
     def train_step(self, cur, ref, target, lr, stream=None):
@@ -545,10 +587,11 @@ class Proposer:
         torch = _torch()
         P, H, W, pitch, stride = _frames(cur, ref)
         loss = torch.empty((1,), dtype=torch.float32, device=cur.device)
-        target = target.contiguous()
+        target = _arg(target.contiguous(), P * (H // 16) * (W // 16) * 2, torch.int16, cur.device, "target")
         rc = lib().me_proposer_train_step(self.h, cur.data_ptr(), ref.data_ptr(), W, H, pitch, stride, P,
                                           target.data_ptr(), float(lr), loss.data_ptr(), _stream(stream))
         _check(rc, "me_proposer_train_step")
+        self._last = (P * (H // 16) * (W // 16) * 3, cur.device)
         return loss
 
     def infer(self, cur, ref, range_, stream=None):
@@ -581,6 +624,9 @@ def dcds_surface(cost, valid=None, algo=ME_ALGO_DCDS, start=None, orient=None, s
     n, side, side2 = cost.shape
     if side != side2 or side % 2 != 1:
         raise ValueError("surfaces must be square with odd side")
+    valid = _arg(valid, n * side * side, torch.uint8, cost.device, "valid")
+    start = _arg(start, 2 * n, torch.int16, cost.device, "start")
+    orient = _arg(orient, n, torch.uint8, cost.device, "orient")
     mv = torch.empty((n, 2), dtype=torch.int16, device=cost.device)
     cout = torch.empty((n,), dtype=torch.int32, device=cost.device)
     nsp = torch.empty((n,), dtype=torch.int32, device=cost.device)

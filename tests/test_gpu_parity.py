@@ -183,6 +183,26 @@ def test_pitch_of_2_23_bytes_and_more():
     torch.cuda.empty_cache()
 
 
+def test_caller_tensors_are_checked_before_any_launch():
+    """Outputs, start vectors and orientations that do not match the block
+    grid raise in the binding; nothing is launched."""
+    cur, ref = random_pair(32, 64, 16, 7, seed=5)
+    tc, tr = to_dev(cur), to_dev(ref)
+    mv = torch.zeros((1, 2, 4, 2), dtype=torch.int16, device=DEV)
+    small = torch.zeros((1, 2, 3), dtype=torch.int32, device=DEV)
+    ok = torch.zeros((1, 2, 4), dtype=torch.int32, device=DEV)
+    with pytest.raises(ValueError):
+        me.dcds(tc, tr, 16, 7, out=(mv, small, ok))
+    with pytest.raises(ValueError):
+        me.fullsearch(tc, tr, 16, 7, out=(mv, ok, ok.to(torch.int16)))
+    with pytest.raises(ValueError):
+        me.dcds(tc, tr, 16, 7, start=torch.zeros((1, 2, 3, 2), dtype=torch.int16, device=DEV))
+    with pytest.raises(ValueError):
+        me.search(tc, tr, 16, 7, sse=True, out=(mv, ok, ok.clone(), small))
+    got = me.dcds(tc, tr, 16, 7, out=(mv, ok, ok.clone()))
+    assert_same(got, oracle_pairs(oracle.dcds, cur[None], ref[None], 16, 7), "checked outputs")
+
+
 def test_zero_pairs_is_a_no_op():
     t = torch.zeros((0, 32, 32), dtype=torch.uint8, device=DEV)
     mv, sad, nsp = me.dcds(t, t, 16, 7)
