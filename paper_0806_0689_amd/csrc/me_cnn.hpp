@@ -40,6 +40,31 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 
 __device__ __forceinline__ v4s as_v4s(uint2 v) { return __builtin_bit_cast(v4s, v); }
 
+// n / D for 0 <= n < N by one 24-bit multiply and a shift, where the
+// compiler's division by a constant takes a 32-bit high multiply: the
+// multiplier is ceil(2^K / D) for the smallest K exact on every n < N
+// (checked here, at compile time, for each n).
+template <int D, int N>
+struct SmallDiv {
+    static constexpr int pick() {
+        for (int k = 0; k < 24; ++k) {
+            const long long m = ((1LL << k) + D - 1) / D;
+            bool ok = (N - 1) * m < (1LL << 24);
+            for (int n = 0; ok && n < N; ++n) ok = ((n * m) >> k) == n / D;
+            if (ok) return k;
+        }
+        return -1;
+    }
+    static constexpr int K = pick();
+    static_assert(K >= 0, "no exact 24-bit multiplier");
+    static constexpr unsigned MUL = (unsigned)(((1LL << K) + D - 1) / D);
+    __device__ static __forceinline__ int div(int n) { return (int)(__umul24((unsigned)n, MUL) >> K); }
+};
+
+// max(x, 0) for finite x as one integer max on the bit pattern (negative
+// floats, -0 included, are negative integers); fmaxf would first quiet x.
+__device__ __forceinline__ float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
 // Two floats to a packed pair of bfloat16 (low = a), each rounded as f2bf.
 typedef float v2f __attribute__((ext_vector_type(2)));
 typedef unsigned int v2u __attribute__((ext_vector_type(2)));
@@ -86,7 +111,8 @@ __global__ __launch_bounds__(256) void k_downdiff(const uint8_t* __restrict__ cu
 
 // ---------------------------------------------------------------------------
 // Forward convolution: out[p][oy][ox][co] = bias[co] + sum_{tap, ci}
-//   in[p][oy*S + ky - 1][ox*S + kx - 1][ci] * W[tap][ci][co]    (tap = 3 ky + kx)
+//   in[p][oy*S + ky - 1][ox*S + kx - 1][ci] * W[tap][ci][co]    (tap = 3 ky + kx),
+// accumulated from the bias.
 // GEMM M = 16 output pixels of one row, N = COUT, K = 9 CIN (k = tap*CIN + ci).
 // Wf: [COUT][KP] bf16, KP = pad16(9 CIN), zero beyond 9 CIN.
 // ---------------------------------------------------------------------------
@@ -102,9 +128,13 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ i
     if (seg * 16 >= Wo) return;
     const int m = lane & 15, kq = lane >> 4;
     const int ox = seg * 16 + m;
+    // The bias is the accumulator's initial value (the fused inference
+    // kernel starts from it too, so both round alike).
     v4f acc[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[t][r] = t * 16 + 4 * kq + r < COUT ? bias[t * 16 + 4 * kq + r] : 0.f;
     const uint16_t* inp = in + (long long)p * Hi * Wi * CIN;
 #pragma unroll 2
     for (int ks = 0; ks < KP / 16; ++ks) {
@@ -134,10 +164,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ i
         if (n0 >= COUT) continue;
         float v[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            v[r] = acc[t][r] + bias[n0 + r];
-            if (RELU) v[r] = fmaxf(v[r], 0.f);
-        }
+        for (int r = 0; r < 4; ++r) v[r] = RELU ? relu(acc[t][r]) : acc[t][r];
         const long long o = (((long long)p * Ho + oy) * Wo + ox) * COUT + n0;
         if (F32OUT) *reinterpret_cast<float4*>(reinterpret_cast<float*>(out) + o) = make_float4(v[0], v[1], v[2], v[3]);
         else *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(out) + o) = make_uint2(pack_bf2(v[0], v[1]), pack_bf2(v[2], v[3]));
@@ -455,7 +482,8 @@ __device__ __forceinline__ void conv_tile(const uint16_t* in, uint16_t* out, flo
 #pragma unroll
             for (int t = 0; t < NT; ++t) w[ks][t] = weights(ks, t);
     }
-    float bn[NT][4];
+    // The bias is each accumulator's initial value.
+    v4f bn[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -467,11 +495,11 @@ __device__ __forceinline__ void conv_tile(const uint16_t* in, uint16_t* out, flo
         // and stores nothing.
         const int po = tile * 16 + m;
         const int pa = min(po, M - 1);
-        const int ay = pa / NO, ax = pa - ay * NO;
+        const int ay = SmallDiv<NO, M>::div(pa), ax = pa - __mul24(ay, NO);
         const uint32_t ab = ib + 2u * (uint32_t)((S * ay * NI + S * ax) * PI) + (CIN >= 16 ? 8u * kq : 0u);
         v4f acc[NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < NT; ++t) acc[t] = bn[t];
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             uint32_t off;
@@ -488,24 +516,23 @@ __device__ __forceinline__ void conv_tile(const uint16_t* in, uint16_t* out, flo
                                                                   acc[t], 0, 0, 0);
         }
         if (po >= M) continue;
-        const bool inside =
-            HEAD || interior || (oy0 + ay >= 0 && oy0 + ay < Ho && ox0 + ax >= 0 && ox0 + ax < Wo);
+        // Outputs outside the layer's grid are the next layer's zero padding;
+        // a tile wholly inside (uniform) skips the test.
+        bool inside = true;
+        if (!HEAD && !interior) inside = oy0 + ay >= 0 && oy0 + ay < Ho && ox0 + ax >= 0 && ox0 + ax < Wo;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             const int n0 = t * 16 + 4 * kq;
             if (n0 >= COUT) continue;
             float v[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                v[r] = acc[t][r] + bn[t][r];
-                if (RELU) v[r] = fmaxf(v[r], 0.f);
-            }
+            for (int r = 0; r < 4; ++r) v[r] = RELU ? relu(acc[t][r]) : acc[t][r];
             if (HEAD) {
-                *lds_ptr<v4f>(ob + 4u * (uint32_t)(po * 4 + n0)) = v4f{v[0], v[1], v[2], v[3]};
+                *lds_ptr<v4f>(ob + (uint32_t)__mul24(po, 16) + 4u * n0) = v4f{v[0], v[1], v[2], v[3]};
             } else {
                 v2u o = v2u{pack_bf2(v[0], v[1]), pack_bf2(v[2], v[3])};
                 if (!inside) o = v2u{0u, 0u};
-                *lds_ptr<v2u>(ob + 2u * (uint32_t)(po * PO + n0)) = o;
+                *lds_ptr<v2u>(ob + (uint32_t)__mul24(po, 2 * PO) + 2u * n0) = o;
             }
         }
     }
