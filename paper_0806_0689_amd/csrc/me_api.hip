@@ -52,6 +52,8 @@ FrameArgs frame_args(const uint8_t* cur, const uint8_t* ref, int32_t width, int3
     a.bh = height / block;
     a.tiles_x = (a.bw + tile_w - 1) / tile_w;
     a.tiles_y = (a.bh + tile_h - 1) / tile_h;
+    a.div_tx = make_divu(a.tiles_x);
+    a.div_ty = make_divu(a.tiles_y);
     return a;
 }
 

@@ -74,11 +74,9 @@ __global__ __launch_bounds__(64 * WPG) void k_dcds_batch(const BatchTable* __res
         for (int t = t0; t < t1; ++t) {
             while (j + 1 < n && tab->jobs[j + 1].tile_begin <= t) ++j;
             const BatchJob& jb = tab->jobs[j];
-            int r = t - jb.tile_begin;
-            const int tx = r % jb.a.tiles_x;
-            r /= jb.a.tiles_x;
-            const int ty = r % jb.a.tiles_y;
-            const int pair = r / jb.a.tiles_y;
+            const int i = t - jb.tile_begin;
+            const int r = jb.a.div_tx.div(i), tx = i - r * jb.a.tiles_x;
+            const int pair = jb.a.div_ty.div(r), ty = r - pair * jb.a.tiles_y;
             if (t != t0) __syncthreads();  // the previous tile's waves are done with LDS
             dcds_tile<B, RPL, WPG, RMAX>(smem, jb.a, jb.flags, pair, tx, ty, jb.start, jb.orient, jb.mv, jb.sad,
                                          jb.nsp, jb.sse);

@@ -29,6 +29,7 @@ struct FrameArgs {
     int R;
     int bw, bh;             // blocks per row / column
     int tiles_x, tiles_y;   // tiles per row / column
+    DivU div_tx, div_ty;    // division by tiles_x, tiles_y
 };
 
 __host__ __device__ constexpr int round_up(int v, int m) { return (v + m - 1) / m * m; }
@@ -351,13 +352,15 @@ __device__ __forceinline__ void dcds_tile(uint32_t* smem, const FrameArgs& a, in
         bd.hix = min(R, a.W - B - x0);
         bd.loy = max(-R, -y0);
         bd.hiy = min(R, a.H - B - y0);
-        const long long idx = ((long long)pair * a.bh + by) * a.bw + bx;
+        // Below 2^31 (a call covers at most 2^31 - 1 blocks), so 2 idx + 1
+        // fits in 32 unsigned bits.
+        const uint32_t idx = (uint32_t)((pair * a.bh + by) * a.bw + bx);
         const bool seeded = start != nullptr;
         int sx = 0, sy = 0;
         bool ov = false;
         if (seeded) {
-            sx = start[2 * idx];
-            sy = start[2 * idx + 1];
+            sx = start[2u * idx];
+            sy = start[2u * idx + 1u];
             ov = orient != nullptr && orient[idx] != 0;
         }
         const bool simp = (flags & DCDS_SIMPLIFIED) != 0;
@@ -369,8 +372,8 @@ __device__ __forceinline__ void dcds_tile(uint32_t* smem, const FrameArgs& a, in
         // Optional epilogue: the squared error of the compensated block.
         const uint32_t e = sse ? ev.sse(ev.a00 + __mul24(r.y, G::WDW * 4) + r.x) : 0u;
         if (g == 0) {
-            mv[2 * idx] = (int16_t)r.x;
-            mv[2 * idx + 1] = (int16_t)r.y;
+            mv[2u * idx] = (int16_t)r.x;
+            mv[2u * idx + 1u] = (int16_t)r.y;
             sad[idx] = r.cost;
             nsp[idx] = r.nsp;
             if (sse) sse[idx] = e;
@@ -384,11 +387,9 @@ __global__ __launch_bounds__(64 * WPG) void k_dcds(FrameArgs a, int flags, const
                                                     uint32_t* __restrict__ sad, uint32_t* __restrict__ nsp,
                                                     uint32_t* __restrict__ sse) {
     extern __shared__ uint32_t smem[];
-    int t = xcd_remap(blockIdx.x, gridDim.x);
-    const int tx = t % a.tiles_x;
-    t /= a.tiles_x;
-    const int ty = t % a.tiles_y;
-    const int pair = t / a.tiles_y;
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const int r = a.div_tx.div(t), tx = t - r * a.tiles_x;
+    const int pair = a.div_ty.div(r), ty = r - pair * a.tiles_y;
     dcds_tile<B, RPL, WPG, RMAX>(smem, a, flags, pair, tx, ty, start, orient, mv, sad, nsp, sse);
 }
 

@@ -82,4 +82,30 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? l
 // Number of 4-byte words of window margin left of a tile for range R.
 __host__ __device__ constexpr int margin_words(int R) { return (R + 3) / 4; }
 
+// Division of 0 <= n < 2^31 by a divisor d >= 1 fixed at launch, as one
+// 32 x 32 -> 64-bit multiply and a shift (scalar instructions when n is
+// uniform; the compiler's division by a run-time value goes through the
+// vector float reciprocal).  With 2^l >= d and m = ceil(2^(31+l) / d),
+// floor(n m / 2^(31+l)) = floor(n / d): m d - 2^(31+l) = e is in [0, d), so
+// the error n e / (d 2^(31+l)) is below 2^-l <= 1/d.  m < 2^32.
+struct DivU {
+    uint32_t m;
+    int s;
+    __host__ __device__ constexpr int div(int n) const { return (int)(((uint64_t)(uint32_t)n * m) >> s); }
+};
+__host__ __device__ constexpr DivU make_divu(int d) {
+    int l = 0;
+    while ((1LL << l) < d) ++l;
+    return DivU{(uint32_t)(((1ULL << (31 + l)) + (uint64_t)d - 1) / (uint64_t)d), 31 + l};
+}
+static_assert(make_divu(1).div(2147483647) == 2147483647, "divide by 1");
+static_assert(make_divu(15).div(2147483647) == 2147483647 / 15, "divide by 15");
+static_assert(make_divu(15).div(14) == 0 && make_divu(15).div(15) == 1, "divide by 15 at the step");
+static_assert(make_divu(9).div(8) == 0 && make_divu(9).div(9) == 1 && make_divu(9).div(2147483646) == 2147483646 / 9,
+              "divide by 9");
+static_assert(make_divu(1 << 20).div(2147483647) == 2047, "divide by a power of two");
+static_assert(make_divu(2147483647).div(2147483646) == 0 && make_divu(2147483647).div(2147483647) == 1,
+              "divide by the largest divisor");
+static_assert(make_divu(1000003).div(1000003 * 2147 - 1) == 2146, "divide by a large prime");
+
 }  // namespace me
