@@ -231,6 +231,22 @@ def test_1080p_all_pairs_dcds_in_one_call(seq1080, B):
 
 
 @pytest.mark.parametrize("B", [16, 8])
+def test_1080p_dcds_with_4_byte_loads(seq1080, B):
+    """Three 1920x1088 pairs read through views 4 bytes off a 16-byte
+    boundary (4-byte loads), so that interior tiles (whose window rows all
+    lie in the frame) and border tiles both take the 4-byte staging."""
+    P = 3
+    big = np.zeros((P + 1, 1088, 1920 + 16), np.uint8)
+    big[:, :, 4:1924] = seq1080[:P + 1]
+    tb = to_dev(big)
+    view = tb[:, :, 4:1924]
+    assert view.data_ptr() % 16 == 4 and view.stride(1) % 16 == 0
+    say("case 1080p 4-byte loads B=%d" % B)
+    got = me.dcds(view[1:], view[:-1], B, 15)
+    assert_same(got, oracle_pairs(oracle.dcds, seq1080[1:P + 1], seq1080[:P], B, 15), "1080p dcds 4-byte loads")
+
+
+@pytest.mark.parametrize("B", [16, 8])
 def test_1080p_fs_sampled_pairs(seq1080, B):
     """FS over all 59 pairs in one call; the oracle checks three sampled pairs."""
     tseq = to_dev(seq1080)
