@@ -282,6 +282,19 @@ ME_EXPORT int me_batch(const me_job* jobs, int32_t n_jobs, int32_t algo, int32_t
     return batch_launch(jobs, n_jobs, algo, block, range, reinterpret_cast<hipStream_t>(stream));
 }
 
+// Records a tuning result, replacing an earlier one for the same device,
+// runtime, block size and range class.
+static void remember(const TuneEntry& e) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    for (auto& t : g_tune) {
+        if (t.arch == e.arch && t.runtime == e.runtime && t.block == e.block && t.rclass == e.rclass) {
+            t = e;
+            return;
+        }
+    }
+    g_tune.push_back(e);
+}
+
 ME_EXPORT int me_autotune(const me_job* jobs, int32_t n_jobs, int32_t algo, int32_t block, int32_t range,
                           int32_t reps, me_config* best, float* best_ms, void* stream) {
     if (algo != ME_ALGO_DCDS && algo != ME_ALGO_DCDS_S) return ME_EUNSUPPORTED;
@@ -341,15 +354,7 @@ ME_EXPORT int me_autotune(const me_job* jobs, int32_t n_jobs, int32_t algo, int3
         e.rpl = top.rows_per_lane;
         e.wpg = top.waves_per_group;
         e.ms = top_ms;
-        std::lock_guard<std::mutex> lock(g_tune_mu);
-        bool replaced = false;
-        for (auto& t : g_tune) {
-            if (t.arch == e.arch && t.runtime == e.runtime && t.block == e.block && t.rclass == e.rclass) {
-                t = e;
-                replaced = true;
-            }
-        }
-        if (!replaced) g_tune.push_back(e);
+        remember(e);
     }
     return ME_OK;
 }
@@ -393,8 +398,7 @@ ME_EXPORT int me_autotune_load(const char* path, int32_t* applied, int32_t* reje
         me_config c{rpl, wpg};
         if (me_set_config(blk, rep_range, &c) == ME_OK) {
             ++n_ok;
-            std::lock_guard<std::mutex> lock(g_tune_mu);
-            g_tune.push_back(TuneEntry{a, rt, blk, rcl, rpl, wpg, ms});
+            remember(TuneEntry{a, rt, blk, rcl, rpl, wpg, ms});
         }
     }
     fclose(f);

@@ -106,6 +106,12 @@ def test_autotune_and_cache_roundtrip(streams, tmp_path):
         rc, applied, rejected = me.me_autotune_load(str(path))
         assert rc == me.ME_OK and applied >= 1 and rejected == 0
         assert me.me_get_config(16, 15) == cfg
+        # A reloaded result replaces the one recorded for the same key.
+        path2 = tmp_path / "tune2.txt"
+        assert me.me_autotune_save(str(path2)) == me.ME_OK
+        rows = [ln.split() for ln in path2.read_text().splitlines() if ln and not ln.startswith("#")]
+        keys = [tuple(r[:4]) for r in rows]
+        assert len(keys) == len(set(keys)), "a reloaded result is recorded twice"
     finally:
         me.set_config(16, 15, None)
 
