@@ -313,8 +313,9 @@ int me_proposer_get_grads(me_proposer *p, float *host, int32_t n);          /* l
 int me_proposer_get_state(me_proposer *p, float *m, float *v, int64_t *step, int32_t n);
 int me_proposer_set_state(me_proposer *p, const float *m, const float *v, int64_t step, int32_t n);
 /* head: device fp32 [n_pairs][height/16][width/16][3].  forward and
- * train_step take at most 65535 pairs and height/4 <= 65535 per call
- * (ME_EUNSUPPORTED beyond).                                                */
+ * train_step take at most 65535 pairs, height/4 <= 65535, and
+ * n_pairs * (height/4) * (width/4) < 2^31 per call (16448 pairs of
+ * 1920x1088; ME_EUNSUPPORTED beyond).                                      */
 int me_proposer_forward(me_proposer *p, const uint8_t *cur, const uint8_t *ref, int32_t width, int32_t height,
                         int32_t pitch, int64_t pair_stride, int32_t n_pairs, float *head, void *stream);
 /* Parameter gradients (me_proposer_get_grads) for a head gradient of the

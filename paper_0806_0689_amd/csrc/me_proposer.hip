@@ -144,8 +144,11 @@ int check_pairs(const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t h
 int forward(me_proposer* p, const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t height, int32_t pitch,
             int64_t pair_stride, int32_t n_pairs, hipStream_t st) {
     const int H4 = height / 4, W4 = width / 4, H8 = H4 / 2, W8 = W4 / 2, H16 = H8 / 2, W16 = W8 / 2;
-    // The per-layer kernels put rows and pairs on grid dimensions y and z.
+    // The per-layer kernels put rows and pairs on grid dimensions y and z;
+    // the weight gradients take one work-item per layer-1 pixel in one
+    // dimension (a dispatch counts work-items in 32 bits).
     if (H4 > 65535 || n_pairs > 65535) return ME_EUNSUPPORTED;
+    if ((long long)n_pairs * H4 * W4 > (long long)INT32_MAX) return ME_EUNSUPPORTED;
     const long long P = n_pairs;
     int rc = ME_OK;
     if ((rc = grow(&p->x0, &p->cx0, (size_t)(P * H4 * W4 * 4))) ||

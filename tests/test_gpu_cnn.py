@@ -211,3 +211,7 @@ def test_forward_grid_limits():
     assert L.me_proposer_forward(p.h, fake, fake, 16, 262160, 16, 16 * 262160, 1, fake, None) == me.ME_EUNSUPPORTED
     assert L.me_proposer_train_step(p.h, fake, fake, 16, 16, 16, 256, 65536, fake, 0.001, fake,
                                     None) == me.ME_EUNSUPPORTED
+    # 16449 pairs of 1920x1088: 2^31 layer-1 pixels or more.
+    W, H = 1920, 1088
+    assert L.me_proposer_train_step(p.h, fake, fake, W, H, W, W * H, 16449, fake, 0.001, fake,
+                                    None) == me.ME_EUNSUPPORTED
