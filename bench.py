@@ -83,8 +83,9 @@ def valu_rates():
     return json.loads(r.stdout.strip().splitlines()[-1])
 
 
-def traffic_for(kernel: str):
-    """HBM bytes per launch measured by rocprofv3 counters, if taken on this source."""
+def counters_for(kernel: str):
+    """The rocprofv3 counter record of a kernel (HBM bytes and VALU
+    instructions per launch), if it was taken on this source."""
     p = os.path.join(ROOT, "profiles", "traffic_%s.json" % kernel)
     if not os.path.exists(p):
         return None
@@ -92,7 +93,30 @@ def traffic_for(kernel: str):
         rec = json.load(f)
     if rec.get("src_digest") != src_digest():
         return None
-    return rec.get("bytes_per_launch")
+    return rec
+
+
+def traffic_for(kernel: str):
+    """HBM bytes per launch measured by rocprofv3 counters, if taken on this source."""
+    rec = counters_for(kernel)
+    return rec.get("bytes_per_launch") if rec else None
+
+
+# VALU issue peak: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4
+# cycles, at the 2.4 GHz peak clock.
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
+
+
+def valu_issue_for(kernel: str, ms: float):
+    """The kernel's VALU instruction count per launch (from its counter
+    record) over this run's launch time, against the issue peak."""
+    rec = counters_for(kernel)
+    if not rec or "valu_insts_per_launch" not in rec:
+        return None
+    rate = rec["valu_insts_per_launch"] / (ms * 1e-3)
+    return {"insts_per_launch": rec["valu_insts_per_launch"], "achieved": rate, "peak": VALU_ISSUE_PEAK,
+            "unit": "wave64 instructions/s", "frac": rate / VALU_ISSUE_PEAK,
+            "lanes_active": rec.get("lanes_active"), "source": rec.get("summary")}
 
 
 _CPU_SEQ = None  # the sequence the forked oracle workers read
@@ -483,6 +507,8 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "bytes_per_block": BYTES_PER_BLOCK(16),
             "traffic": traffic_for("k_dcds_1080p"),
+            # What bounds the kernel in practice: its VALU issue rate.
+            "valu_issue": valu_issue_for("k_dcds_1080p", d["ms_per_step"]),
         },
         "cpu_baseline": None,
     }
