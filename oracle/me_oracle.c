@@ -177,29 +177,23 @@ static pt dcds_from(search_state *st, pt start, int first_vertical, int variant,
      * current pattern is the motion vector.                                 */
     const pt *mid = (p == PAT_H) ? MID_H : MID_V;
     if (variant == OR_VARIANT_DCDS_S) {
-        /* Simplified DCDS (§IV-C): compare the two distant points and check
-         * only the middle point on the side of the smaller one.  Reading:
-         * the negative side wins a tie; if only one distant point is in V,
-         * its side is checked; if neither is, both middles are tried.       */
+        /* Simplified DCDS (§IV-C): the distortions of the two distant points
+         * are compared, and only the middle point on the side of the smaller
+         * one is checked; a tie goes to the negative side.  Reading: when a
+         * distant point lies outside V there is no comparison to use, so both
+         * middle points are checked, as in plain DCDS.                      */
         pt dn = {c.dx + 2 * mid[0].dx, c.dy + 2 * mid[0].dy};
         pt dp = {c.dx + 2 * mid[1].dx, c.dy + 2 * mid[1].dy};
         int64_t sn = 0, sp = 0;
         int vn = eval_point(st, dn.dx, dn.dy, &sn);
         int vp = eval_point(st, dp.dx, dp.dy, &sp);
-        pt pick[2];
-        int npick = 0;
-        if (vn && vp)
-            pick[npick++] = (sp < sn) ? mid[1] : mid[0];
-        else if (vn)
-            pick[npick++] = mid[0];
-        else if (vp)
-            pick[npick++] = mid[1];
-        else {
-            pick[npick++] = mid[0];
-            pick[npick++] = mid[1];
+        pt list[3] = {{0, 0}, mid[0], mid[1]};
+        int n = 3;
+        if (vn && vp) {
+            list[1] = (sp < sn) ? mid[1] : mid[0];
+            n = 2;
         }
-        pt list[3] = {{0, 0}, pick[0], npick > 1 ? pick[1] : pick[0]};
-        b = pattern_bmp(st, c, list, 1 + npick, &d);
+        b = pattern_bmp(st, c, list, n, &d);
     } else {
         pt list[3] = {{0, 0}, mid[0], mid[1]};
         b = pattern_bmp(st, c, list, 3, &d);
@@ -209,16 +203,22 @@ static pt dcds_from(search_state *st, pt start, int first_vertical, int variant,
     return b;
 }
 
-/* Learned start (not part of the paper's method): probe the origin and the
- * proposed start s.  If s is the origin or does not beat it, run plain DCDS
- * from the origin; otherwise run DCDS with its first cross centred at s.  */
+/* Learned start (not part of the paper's method).  Plain DCDS runs first,
+ * from the origin.  Then the proposed start s is probed; only if it beats
+ * the plain result does DCDS run a second time, with its first cross (HCSP,
+ * or its transpose when orient_v) centred at s, over the same set S: a point
+ * already in S keeps its distortion and is not counted again.  Every point of
+ * S is then worse than the second search's centre, so the result is never
+ * worse than plain DCDS's.                                                  */
 static pt dcds_seeded(search_state *st, pt s, int orient_v, int variant, int64_t *bdm_out)
 {
-    int64_t d0, ds;
+    int64_t dp, ds;
     pt origin = {0, 0};
-    eval_point(st, 0, 0, &d0);
-    if (same_pt(s, origin) || !eval_point(st, s.dx, s.dy, &ds) || ds >= d0)
-        return dcds_from(st, origin, 0, variant, bdm_out);
+    pt p = dcds_from(st, origin, 0, variant, &dp);
+    if (same_pt(s, origin) || !eval_point(st, s.dx, s.dy, &ds) || ds >= dp) {
+        *bdm_out = dp;
+        return p;
+    }
     return dcds_from(st, s, orient_v, variant, bdm_out);
 }
 

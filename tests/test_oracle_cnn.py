@@ -107,3 +107,50 @@ def test_shapes_and_counts():
     assert x0.shape == (272, 480, 2)
     head, acts = cnn.forward(x0, cnn.init_params(0))
     assert head.shape == (68, 120, 3) and [a.shape[2] for a in acts] == [2, 16, 32, 32]
+
+
+def test_downdiff_on_known_box_means():
+    """x0 from frames whose 4x4 box means are known by construction: each 4x4
+    box of cur holds four copies of a, b, c, d (mean (a+b+c+d)/4), ref a
+    constant; channel 0 is (mean - ref) / 32, channel 1 (mean - 128) / 64."""
+    rng = np.random.default_rng(5)
+    hb, wb = 3, 5
+    vals = rng.integers(0, 256, (hb, wb, 4))
+    cur = np.zeros((4 * hb, 4 * wb), np.uint8)
+    for j in range(hb):
+        for i in range(wb):
+            box = np.repeat(vals[j, i], 4).reshape(4, 4)  # rows a a a a / b b b b / ...
+            cur[4 * j:4 * j + 4, 4 * i:4 * i + 4] = box
+    ref = np.full_like(cur, 100)
+    x = cnn.downdiff(cur, ref, round_=False)
+    mean = vals.sum(axis=-1) / 4.0
+    assert x.shape == (hb, wb, 2)
+    np.testing.assert_array_equal(x[..., 0], (mean - 100.0) / 32.0)
+    np.testing.assert_array_equal(x[..., 1], (mean - 128.0) / 64.0)
+    # A box is never mixed with its neighbours: one changed pixel moves one cell.
+    cur2 = cur.copy()
+    cur2[5, 9] = cur2[5, 9] ^ 4
+    d = cnn.downdiff(cur2, ref, round_=False) - x
+    assert np.count_nonzero(d[..., 0]) == 1 and d[1, 2, 0] != 0
+    # Rounded input: the bf16 value nearest the exact one (8 significant bits).
+    xr = cnn.downdiff(cur, ref)
+    assert np.all(np.abs(xr - x) <= np.abs(x) * 2.0 ** -8)
+
+
+def test_decode_rounding_and_clamp():
+    """Start = 8 (u, v) rounded half to even (rint), clamped to +-R; vertical
+    when o > 0 (o = 0 is horizontal)."""
+    u = np.array([0.0625, 0.1875, 0.3125, -0.0625, -0.1875, 0.06, 0.07, 10.0, -10.0, 1.9375])
+    # 8u = 0.5, 1.5, 2.5, -0.5, -1.5, 0.48, 0.56, 80, -80, 15.5
+    want = np.array([0, 2, 2, 0, -2, 0, 1, 15, -15, 15])
+    head = np.zeros((1, len(u), 3))
+    head[0, :, 0] = u
+    head[0, :, 1] = -u
+    head[0, :, 2] = np.array([1e-9, 0.0, -1e-9, 5, -5, 0, 0, 0, 0, 0])
+    s, o = cnn.decode(head, 15)
+    np.testing.assert_array_equal(s[0, :, 0], want)
+    np.testing.assert_array_equal(s[0, :, 1], -want)
+    np.testing.assert_array_equal(o[0], [1, 0, 0, 1, 0, 0, 0, 0, 0, 0])
+    s7, _ = cnn.decode(head, 7)
+    np.testing.assert_array_equal(s7[0, :, 0], np.clip(want, -7, 7))
+    assert s.dtype == np.int16 and o.dtype == np.uint8

@@ -100,8 +100,8 @@ def test_simplified_dcds_relations():
 
 def test_seeded_start_relations():
     """Learned start (not in the paper): a zero start is plain DCDS; a start that
-    does not beat the origin falls back to plain DCDS (plus its probe point); a
-    start that wins is never worse than itself."""
+    does not beat plain DCDS's result leaves that result (plus its probe point);
+    a start that does is never worse than itself."""
     seq = make_config(2, frames=2)
     cur, ref = seq[1], seq[0]
     B, R = 16, 7
@@ -125,8 +125,8 @@ def test_seeded_start_relations():
             xs = np.nonzero(valid.any(axis=0))[0] - R
             ys = np.nonzero(valid.any(axis=1))[0] - R
             s = (int(np.clip(start[j, i, 0], xs.min(), xs.max())), int(np.clip(start[j, i, 1], ys.min(), ys.max())))
-            d0, ds = cost[R, R], cost[s[1] + R, s[0] + R]
-            if s == (0, 0) or ds >= d0:
+            ds = cost[s[1] + R, s[0] + R]
+            if s == (0, 0) or ds >= sad[j, i]:
                 _, _, _, S = oracle.dcds_surface(cost, valid, want_set=True)
                 assert tuple(m1[j, i]) == tuple(mv[j, i]) and s1[j, i] == sad[j, i]
                 assert n1[j, i] == nsp[j, i] + (0 if S[s[1] + R, s[0] + R] else 1)

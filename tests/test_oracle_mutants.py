@@ -11,6 +11,7 @@ import pytest
 import oracle
 from conftest import load_golden
 from test_oracle_bruteforce import _frames, brute_fs
+from test_oracle_rules import PINS as RULE_PINS
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "me_oracle.c")
 
@@ -37,6 +38,17 @@ MUTANTS = {
     "frame_edge": ("x <= f->W - f->B", "x < f->W - f->B"),
     # Reference rows taken from the current frame's row (dy ignored in SAD).
     "sad_row": ("(size_t)(f->y0 + dy + v) * f->pitch", "(size_t)(f->y0 + v) * f->pitch"),
+    # DCDS^S: the middle point on the side of the larger distant point.
+    "dcds_s_side_flip": ("list[1] = (sp < sn) ? mid[1] : mid[0];", "list[1] = (sp < sn) ? mid[0] : mid[1];"),
+    # DCDS^S: with one distant point outside V, only the valid partner's side.
+    "dcds_s_edge_one_side": ("        if (vn && vp) {\n            list[1] = (sp < sn) ? mid[1] : mid[0];",
+                             "        if (vn || vp) {\n            list[1] = (vn && vp ? sp < sn : vp) ? mid[1] : mid[0];"),
+    # Learned start: the proposer's orientation ignored (always HCSP).
+    "seeded_vcsp_ignored": ("first_vertical ? VCSP : HCSP", "HCSP"),
+    # Learned start: the start followed whenever it beats the origin.
+    "seeded_gate_origin": ("|| ds >= dp)", "|| ds >= st->bdm[widx(st, 0, 0)])"),
+    # Learned start: the start always followed (no fallback to plain DCDS).
+    "seeded_no_fallback": ("|| ds >= dp)", "|| 0)"),
 }
 
 
@@ -78,8 +90,17 @@ def _brute_ok():
     return True
 
 
+def _rules_ok():
+    for pin in RULE_PINS:
+        try:
+            pin()
+        except AssertionError:
+            return False
+    return True
+
+
 def _all_pins_ok():
-    return _table7_ok() and _brute_ok()
+    return _table7_ok() and _brute_ok() and _rules_ok()
 
 
 def test_real_oracle_passes_pins():
