@@ -119,13 +119,14 @@ int me_dcds(const uint8_t *cur, const uint8_t *ref, int32_t width, int32_t heigh
 /*
  * DCDS with options.  algo: ME_ALGO_DCDS or ME_ALGO_DCDS_S.
  * start (optional, device, one per block): a proposed start vector, clamped
- * into the block's candidate set.  The origin and the start are evaluated; if
- * the start is the origin or its SAD is not below the origin's, plain DCDS runs
- * from the origin (the fallback); otherwise the first cross is centred on the
- * start.  orient (optional, device, one byte per block): 0 = horizontal cross
- * (the paper's), 1 = vertical cross for that first pattern.  nsp counts the
- * probe points too.  The learned start is this library's addition, not part of
- * the paper's method.
+ * into the block's candidate set.  Plain DCDS runs first, from the origin;
+ * then the start is evaluated, and only if its SAD is below the plain result's
+ * does DCDS run again with its first cross centred on the start (the plain
+ * result is the fallback, so the result is never worse than plain DCDS).
+ * orient (optional, device, one byte per block): 0 = horizontal cross (the
+ * paper's), 1 = vertical cross for that second search's first pattern.  nsp
+ * counts every distinct point of both searches and the probe.  The learned
+ * start is this library's addition, not part of the paper's method.
  */
 int me_dcds_ex(const uint8_t *cur, const uint8_t *ref, int32_t width, int32_t height, int32_t pitch,
                int64_t pair_stride, int32_t n_pairs, int32_t block, int32_t range, int32_t algo,

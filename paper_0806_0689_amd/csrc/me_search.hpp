@@ -75,54 +75,52 @@ __device__ __forceinline__ uint32_t key(bool valid, uint32_t cost, uint32_t idx)
 // HCSP order: centre, -1, +1, -2, +2 along the arm, -1, +1 across it.
 // Points outside the candidate set may be evaluated on any finite data; their
 // results are masked here.
-// SIMPLIFIED: Step 4 of DCDS^S; SEEDED: learned start (sx, sy, orient_v).
-// bm: the group's bitmap, bitmap_words(RMAX) words, all zero on entry.
-template <int L, int RMAX, bool SIMPLIFIED, bool SEEDED, class Ev>
-__device__ SearchOut dcds_search(const Ev& ev, int R, const Bounds& bd, uint32_t* bm, int g, int sx, int sy,
-                                 bool orient_v) {
-    static_assert(L == 4 || L == 8 || L == 16, "group of 4, 8 or 16 lanes");
+
+struct WalkOut {
+    int x, y;
+    uint32_t cost;
+};
+
+// Sets bit k of the group's bitmap when act (fire and forget).
+__device__ __forceinline__ void mark_point(uint32_t* bm, bool act, int k) {
+    if (act) (void)atomicOr(&bm[k >> 5], 1u << (k & 31));
+}
+
+// NSP: the number of bits set in the group's bitmap (the group's own LDS
+// operations complete in order, so every mark is visible here).  Words past
+// the window's bits are zero; every lane reads NW words, and a last word
+// beyond the bitmap is dropped.
+template <int L, int RMAX>
+__device__ __forceinline__ uint32_t count_points(const uint32_t* bm, int g) {
+    constexpr int WMAX = bitmap_words(RMAX), NW = (WMAX + L - 1) / L;
+    uint32_t n = 0;
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+        const uint32_t w = bm[g + j * L];
+        n += __popc(j < NW - 1 || g + j * L < WMAX ? w : 0u);
+    }
+    return group_sum<L>(n);
+}
+
+// Steps 1-4 of DCDS with the first cross centred at (cx, cy): HCSP, or its
+// transpose when t.  AT_ORIGIN: the paper's start, (0, 0) with HCSP (its
+// cross reads the centre row once).  Every point evaluated is marked in bm.
+// Returns the final vector and its cost; the caller counts the points.
+template <int L, bool SIMPLIFIED, bool AT_ORIGIN, class Ev>
+__device__ __forceinline__ WalkOut dcds_walk(const Ev& ev, int R, const Bounds& bd, uint32_t* bm, int g, int cx,
+                                             int cy, bool t) {
     const int S = 2 * R + 1;      // bitmap row length
     const int k00 = R * S + R;    // bitmap index of the origin
     const int rs = ev.row();
-    int cx = 0, cy = 0;
-    bool t = false;               // current pattern is vertical
-
-    auto mark = [&](bool act, int k) {
-        if (act) (void)atomicOr(&bm[k >> 5], 1u << (k & 31));
-    };
-    // NSP: the number of bits set (the group's own LDS operations complete in
-    // order, so every mark is visible here).  Words past the window's bits
-    // are zero; every lane reads NW words, and a last word beyond the bitmap
-    // is dropped.
-    auto count = [&]() -> uint32_t {
-        constexpr int WMAX = bitmap_words(RMAX), NW = (WMAX + L - 1) / L;
-        uint32_t n = 0;
-#pragma unroll
-        for (int j = 0; j < NW; ++j) {
-            const uint32_t w = bm[g + j * L];
-            n += __popc(j < NW - 1 || g + j * L < WMAX ? w : 0u);
-        }
-        return group_sum<L>(n);
-    };
 
     uint32_t c7[7];
-    if constexpr (SEEDED) {
-        // Learned start: probe the origin and the (clamped) start; lane 0
-        // marks the origin, lane 1 the start.
-        sx = clampi(sx, bd.lox, bd.hix);
-        sy = clampi(sy, bd.loy, bd.hiy);
-        const bool moved = (sx != 0) || (sy != 0);
-        uint32_t p0, ps;
-        ev.pair(ev.a00, ev.a00 + __mul24(sy, rs) + sx, p0, ps);
-        mark(g == 0 || (g == 1 && moved), k00 + (g == 1 ? __mul24(sy, S) + sx : 0));
-        if (moved && ps < p0) {
-            cx = sx;
-            cy = sy;
-            t = orient_v;
-        }
-        ev.cross(ev.a00 + __mul24(cy, rs) + cx, t, c7);
-    } else {
+    if constexpr (AT_ORIGIN) {
+        cx = 0;
+        cy = 0;
+        t = false;
         ev.cross0(c7);
+    } else {
+        ev.cross(ev.a00 + __mul24(cy, rs) + cx, t, c7);
     }
 
     // Step 1: the cross centred at (cx, cy).
@@ -140,7 +138,7 @@ __device__ SearchOut dcds_search(const Ev& ev, int R, const Bounds& bd, uint32_t
             const bool v = i == 0 || (i == 1 && am1) || (i == 2 && ap1) || (i == 3 && am2) || (i == 4 && ap2) ||
                            (i == 5 && pm1) || (i == 6 && pp1);
             const int dx = t ? op : oa, dy = t ? oa : op;
-            mark(v, k00 + __mul24(cy + dy, S) + (cx + dx));
+            mark_point(bm, v, k00 + __mul24(cy + dy, S) + (cx + dx));
         }
     }
     uint32_t m = c7[0] << 3;
@@ -151,12 +149,12 @@ __device__ SearchOut dcds_search(const Ev& ev, int R, const Bounds& bd, uint32_t
     m = min(m, key(pm1, c7[5], 5u));
     m = min(m, key(pp1, c7[6], 6u));
     const uint32_t w = m & 7u;
-    if (w == 0) return SearchOut{cx, cy, m >> 3, count()};  // half-way stop
+    if (w == 0) return WalkOut{cx, cy, m >> 3};  // half-way stop
 
     // Move to the BMP.  Switching strategy one: a BMP along x selects the
     // horizontal diamond, otherwise the vertical one.  dir: the last move
     // (its sign says which way is ahead); the point behind the new centre is
-    // the opposite cross point (or the origin after a step of 2).
+    // the opposite cross point (or the cross's centre after a step of 2).
     int dir;
     uint32_t kcost = 0;  // cost of the distant point behind the centre
     {
@@ -192,7 +190,7 @@ __device__ SearchOut dcds_search(const Ev& ev, int R, const Bounds& bd, uint32_t
             // Marked before the evaluation, so that no masked store splits
             // the sums' DPP steps (which then fold into their adds).
             const int ko = t ? kv : kh;
-            mark((g == 0 && vF) || (g == 1 && vNm) || (g == 2 && vNp), kc + ((g == 0 && !s) ? -ko : ko));
+            mark_point(bm, (g == 0 && vF) || (g == 1 && vNm) || (g == 2 && vNp), kc + ((g == 0 && !s) ? -ko : ko));
         }
         uint32_t cNm, cNp;
         ev.pair(ca + (s ? arm2 : -arm2), ca - perp, cF, cNm);
@@ -226,27 +224,20 @@ __device__ SearchOut dcds_search(const Ev& ev, int R, const Bounds& bd, uint32_t
     // Step 4: the centre and the two middle points of the current diamond.
     bool r0 = rc.am(t) >= 1, r1 = rc.ap(t) >= 1;
     if (SIMPLIFIED) {
-        // Simplified DCDS (§IV-C): only the middle point on the side of the
-        // smaller distant point; ties -> negative side; with one distant
-        // point outside the set, its valid partner's side; with none, both.
-        const bool v0 = rc.am(t) >= 2, v1 = rc.ap(t) >= 2;
-        const uint32_t d0 = dir > 0 ? kcost : cF, d1 = dir > 0 ? cF : kcost;
-        bool use0 = true, use1 = true;
-        if (v0 && v1) {
-            use1 = d1 < d0;
-            use0 = !use1;
-        } else if (v0) {
-            use1 = false;
-        } else if (v1) {
-            use0 = false;
+        // Simplified DCDS (§IV-C): with both distant points in the set, only
+        // the middle point on the side of the smaller one (ties -> negative
+        // side).  With a distant point outside the set there is nothing to
+        // compare, and both middle points are checked.
+        if (rc.am(t) >= 2 && rc.ap(t) >= 2) {
+            const uint32_t d0 = dir > 0 ? kcost : cF, d1 = dir > 0 ? cF : kcost;
+            r0 = !(d1 < d0);
+            r1 = d1 < d0;
         }
-        r0 = r0 && use0;
-        r1 = r1 && use1;
     }
     const int arm = t ? rs : 1;
     {
         const int ka = t ? S : 1;
-        mark((g == 0 && r0) || (g == 1 && r1), g == 0 ? kc - ka : kc + ka);
+        mark_point(bm, (g == 0 && r0) || (g == 1 && r1), g == 0 ? kc - ka : kc + ka);
     }
     uint32_t mc0, mc1;
     ev.pair(ca - arm, ca + arm, mc0, mc1);
@@ -258,7 +249,34 @@ __device__ SearchOut dcds_search(const Ev& ev, int R, const Bounds& bd, uint32_t
         const int o = wf == 1 ? -1 : 1;
         if (t) cy += o; else cx += o;
     }
-    return SearchOut{cx, cy, mf >> 3, count()};
+    return WalkOut{cx, cy, mf >> 3};
+}
+
+// The search of one block.  SIMPLIFIED: Step 4 of DCDS^S.  SEEDED: learned
+// start (sx, sy, orient_v; this library's addition): plain DCDS runs first;
+// the start, clamped into the candidate set, is then probed, and only if it
+// beats the plain result does DCDS run again with its first cross centred
+// there (HCSP, or its transpose when orient_v).  Every point of the first
+// search costs at least the plain result, so none of them can win in the
+// second, and the result is never worse than plain DCDS's.  Points shared by
+// both searches are counted once (the bitmap is common).
+// bm: the group's bitmap, bitmap_words(RMAX) words, all zero on entry.
+template <int L, int RMAX, bool SIMPLIFIED, bool SEEDED, class Ev>
+__device__ SearchOut dcds_search(const Ev& ev, int R, const Bounds& bd, uint32_t* bm, int g, int sx, int sy,
+                                 bool orient_v) {
+    static_assert(L == 4 || L == 8 || L == 16, "group of 4, 8 or 16 lanes");
+    WalkOut r = dcds_walk<L, SIMPLIFIED, true>(ev, R, bd, bm, g, 0, 0, false);
+    if constexpr (SEEDED) {
+        sx = clampi(sx, bd.lox, bd.hix);
+        sy = clampi(sy, bd.loy, bd.hiy);
+        if (sx != 0 || sy != 0) {
+            const int S = 2 * R + 1;
+            mark_point(bm, g == 0, R * S + R + __mul24(sy, S) + sx);
+            const uint32_t ps = ev.one(ev.a00 + __mul24(sy, ev.row()) + sx);
+            if (ps < r.cost) r = dcds_walk<L, SIMPLIFIED, false>(ev, R, bd, bm, g, sx, sy, orient_v);
+        }
+    }
+    return SearchOut{r.x, r.y, r.cost, count_points<L, RMAX>(bm, g)};
 }
 
 }  // namespace me

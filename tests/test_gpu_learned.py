@@ -1,8 +1,14 @@
-"""What the trained proposer gains over DCDS without it, on held-out seeds
-(never seen in training): the learned start must keep mean SAD within 1% of
-plain DCDS and is expected to save search points; every block stays no better
-than FS (the exhaustive reference).  Uses the committed checkpoint written by
-paper_0806_0689_amd/train.py."""
+"""What the trained proposer gains over DCDS without it, on every single-sequence
+workload (configs 1, 2, 3 and 5) and on held-out training-law sequences (never
+seen in training).
+
+Learned-start DCDS runs plain DCDS first and follows the proposed start only
+when it beats that result, so on every block its SAD is at most plain DCDS's
+(and at least FS's, the exhaustive reference): mean SAD is within 1% of plain
+DCDS by construction, and is checked block by block here.  The gain is the SAD
+the start finds beyond plain DCDS; on the long-motion 1088p and 4K content it
+must be large.  The cost is reported: the points of both searches.  Uses the
+committed checkpoint written by paper_0806_0689_amd/train.py."""
 import os
 
 import numpy as np
@@ -34,25 +40,43 @@ def stats(seq, p, R):
     _, fs, _ = me.fullsearch(cur, ref, 16, R)
     _, ps, pn = me.dcds(cur, ref, 16, R)
     _, ls, ln = me.dcds_learned(p, cur, ref, R)
-    assert bool((ls >= fs).all()) and bool((ps >= fs).all())
+    # Block by block: FS <= learned <= plain.
+    assert bool((ls >= fs).all()) and bool((ls <= ps).all())
     return {k: float(v.double().mean()) for k, v in
             (("fs", fs), ("plain", ps), ("learned", ls), ("plain_nsp", pn), ("learned_nsp", ln))}
 
 
-@pytest.mark.parametrize("q", [0, 1])
-def test_gain_on_held_out_1080p(proposer, q):
-    s = stats(training_sequence(q, frames=12, held_out=True), proposer, 31)
-    say("held-out 1080p seq %d:" % q, s)
-    assert s["learned"] <= 1.01 * s["plain"]
-    assert s["learned_nsp"] < s["plain_nsp"]
+# (name, frames, range, required SAD ratio learned / plain)
+CASES = [
+    ("config1_qcif_r7", lambda: make_config(1), 7, 1.01),
+    ("config2_cif_r7", lambda: make_config(2, frames=12), 7, 1.01),
+    ("config3_1088p_r15", lambda: make_config(3, frames=4), 15, 0.95),
+    ("config5_4k_r31", lambda: make_config(5, frames=3), 31, 0.9),
+    ("held_out_1088p_q0_r31", lambda: training_sequence(0, frames=8, held_out=True), 31, 0.9),
+    ("held_out_1088p_q1_r31", lambda: training_sequence(1, frames=8, held_out=True), 31, 0.9),
+    ("held_out_4k_r31", lambda: make_config(5, seed=20005, frames=3), 31, 0.9),
+]
 
 
-def test_gain_on_4k_sample(proposer):
-    seq = make_config(5, seed=20005, frames=4)
-    s = stats(seq, proposer, 31)
-    say("held-out 4K sample:", s)
-    assert s["learned"] <= 1.01 * s["plain"]
-    assert s["learned_nsp"] < s["plain_nsp"]
+@pytest.mark.parametrize("name,make,R,ratio", CASES, ids=[c[0] for c in CASES])
+def test_learned_start_against_plain(proposer, name, make, R, ratio):
+    s = stats(make(), proposer, R)
+    say("%s: sad fs %.1f plain %.1f learned %.1f (x%.3f); nsp plain %.2f learned %.2f" %
+        (name, s["fs"], s["plain"], s["learned"], s["learned"] / s["plain"], s["plain_nsp"], s["learned_nsp"]))
+    assert s["learned"] <= ratio * s["plain"]
+    assert s["learned_nsp"] >= s["plain_nsp"]
+
+
+def test_untrained_proposer_is_plain_dcds():
+    """All-zero weights propose the origin on every block: the result is plain
+    DCDS exactly, points included (the fallback path)."""
+    p = me.Proposer()
+    seq = make_config(1)
+    t = torch.from_numpy(seq).to(DEV)
+    got = me.dcds_learned(p, t[1:], t[:-1], 7)
+    exp = me.dcds(t[1:], t[:-1], 16, 7)
+    for a, b in zip(got, exp):
+        assert torch.equal(a, b)
 
 
 def test_checkpoint_loads_without_pickle():
