@@ -261,6 +261,21 @@ typedef struct {
 int me_batch(const me_job *jobs, int32_t n_jobs, int32_t algo, int32_t block, int32_t range, void *stream);
 
 /*
+ * me_batch for callers that cannot allocate: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Same arguments and
+ * results as me_batch, but the library allocates nothing on any call: the job
+ * table and the tile counter live in one fixed device array of this library
+ * (about 64 KiB, held by every GPU the library runs on until the process
+ * ends), filled by small kernels on `stream` whose arguments carry the table.
+ * At most 512 jobs and 2^30 work tiles per call (ME_EUNSUPPORTED beyond).
+ * Every call on one GPU shares that array: calls must not overlap on a GPU
+ * (issue them on one stream, or order their streams); overlapping calls race
+ * and give undefined results.  The first call on a device looks the array up
+ * (hipGetSymbolAddress); later calls only launch.
+ */
+int me_batch_noalloc(const me_job *jobs, int32_t n_jobs, int32_t algo, int32_t block, int32_t range, void *stream);
+
+/*
  * Autotuner: times every DCDS kernel configuration (me_config) on the given
  * batch with `reps` launches each (me_batch on `stream`, synchronising it),
  * keeps the fastest for (block, range class) via me_set_config, and returns it

@@ -43,6 +43,7 @@ EXPORTS = [
     "me_mvp_tables_size",
     "me_mvp_tables",
     "me_batch",
+    "me_batch_noalloc",
     "me_autotune",
     "me_autotune_save",
     "me_autotune_load",
@@ -131,6 +132,8 @@ def lib() -> ctypes.CDLL:
         L.me_get_config.restype = ctypes.c_int
         L.me_batch.argtypes = [ctypes.POINTER(MeJob), i32, i32, i32, i32, vp]
         L.me_batch.restype = ctypes.c_int
+        L.me_batch_noalloc.argtypes = [ctypes.POINTER(MeJob), i32, i32, i32, i32, vp]
+        L.me_batch_noalloc.restype = ctypes.c_int
         L.me_autotune.argtypes = [ctypes.POINTER(MeJob), i32, i32, i32, i32, i32, ctypes.POINTER(MeConfig),
                                   ctypes.POINTER(ctypes.c_float), vp]
         L.me_autotune.restype = ctypes.c_int
@@ -235,6 +238,11 @@ def me_get_config(block, range_):
 def me_batch(jobs, n_jobs, algo, block, range_, stream=0):
     """jobs: a ctypes array of MeJob (or None)."""
     return lib().me_batch(jobs, n_jobs, algo, block, range_, stream)
+
+
+def me_batch_noalloc(jobs, n_jobs, algo, block, range_, stream=0):
+    """jobs: a ctypes array of MeJob (or None).  Allocates nothing in the library."""
+    return lib().me_batch_noalloc(jobs, n_jobs, algo, block, range_, stream)
 
 
 def me_autotune(jobs, n_jobs, algo, block, range_, reps, stream=0):
@@ -494,6 +502,15 @@ def batch(pairs, block=16, range_=15, algo=ME_ALGO_DCDS, starts=None, orients=No
     """One persistent launch over many sequences; returns one (mv, sad, nsp) per job."""
     jobs, outputs = make_jobs(pairs, block, starts, orients, outs, sses)
     _check(me_batch(jobs, len(pairs), algo, block, range_, _stream(stream)), "me_batch")
+    return outputs
+
+
+def batch_noalloc(pairs, block=16, range_=15, algo=ME_ALGO_DCDS, starts=None, orients=None, outs=None, sses=None,
+                  stream=None):
+    """me_batch_noalloc over (cur, ref) pairs; outputs as batch() (allocated
+    here by torch unless given in outs)."""
+    jobs, outputs = make_jobs(pairs, block, starts, orients, outs, sses)
+    _check(me_batch_noalloc(jobs, len(pairs), algo, block, range_, _stream(stream)), "me_batch_noalloc")
     return outputs
 
 

@@ -14,6 +14,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <string>
@@ -158,7 +159,11 @@ int enqueue(Slot& s, const Variant& v, unsigned grid, size_t table_bytes, hipStr
     return ME_OK;
 }
 
-int batch_launch(const me_job* jobs, int32_t n_jobs, int32_t algo, int32_t block, int32_t range, hipStream_t st) {
+// Argument checks shared by me_batch and me_batch_noalloc (nothing is
+// launched on an error).  Returns the kernel kind, its configuration (rows
+// per lane, waves per group) and the tile shape in blocks.
+int check_batch(const me_job* jobs, int32_t n_jobs, int32_t algo, int32_t block, int32_t range, int* kind,
+                int* rpl, int* wpg, int* tile_w, int* tile_h) {
     if (n_jobs < 0 || n_jobs > kMaxJobs) return ME_EINVAL;
     if (algo != ME_ALGO_FS && algo != ME_ALGO_DCDS && algo != ME_ALGO_DCDS_S) return ME_EUNSUPPORTED;
     if (block != 8 && block != 16) return ME_EUNSUPPORTED;
@@ -172,10 +177,61 @@ int batch_launch(const me_job* jobs, int32_t n_jobs, int32_t algo, int32_t block
         if (j.orient && !j.start) return ME_EINVAL;
         if (algo == ME_ALGO_FS && (j.start || j.orient)) return ME_EINVAL;
     }
-    const int kind = algo == ME_ALGO_FS ? KIND_FS : KIND_DCDS;
-    int rpl = 1, wpg = 1;
-    if (kind == KIND_DCDS) current_cfg(block, range_class(range), &rpl, &wpg);
-    const int tile_w = kind == KIND_FS ? 1 : 64 * rpl / block, tile_h = kind == KIND_FS ? 1 : wpg;
+    *kind = algo == ME_ALGO_FS ? KIND_FS : KIND_DCDS;
+    *rpl = 1;
+    *wpg = 1;
+    if (*kind == KIND_DCDS) current_cfg(block, range_class(range), rpl, wpg);
+    *tile_w = *kind == KIND_FS ? 1 : 64 * *rpl / block;
+    *tile_h = *kind == KIND_FS ? 1 : *wpg;
+    return ME_OK;
+}
+
+// The device record of one job whose tiles start at tile_begin.
+BatchJob make_job(const me_job& j, int32_t algo, int32_t block, int32_t range, int tile_w, int tile_h,
+                  long long tile_begin) {
+    BatchJob b;
+    b.a = frame_args(j.cur, j.ref, j.width, j.height, j.pitch, j.pair_stride, block, range, tile_w, tile_h);
+    b.flags = dcds_flags(algo, j.cur, j.ref, j.width, j.pitch, j.pair_stride);
+    b.tile_begin = (int)tile_begin;
+    b.start = reinterpret_cast<const int16_t*>(j.start);
+    b.orient = j.orient;
+    b.mv = reinterpret_cast<int16_t*>(j.mv);
+    b.sad = j.sad;
+    b.nsp = j.nsp;
+    b.sse = j.sse;
+    return b;
+}
+
+long long job_tiles(const BatchJob& b, int n_pairs) { return (long long)b.a.tiles_x * b.a.tiles_y * n_pairs; }
+
+// The shared tile counter runs past the total by kBatchChunk for every
+// workgroup before each has seen the end: 2^30 keeps it far from int
+// overflow.
+constexpr long long kMaxTiles = 1LL << 30;
+
+// Grid of a persistent kernel: resident workgroups per CU x CUs.  The
+// persistent kernels also hold a little static LDS (the grabbed tile index):
+// their dynamic limit leaves room for it.
+int persistent_grid(const Variant& v, int cus, unsigned* grid) {
+    if (v.lds > 65536 && hipFuncSetAttribute(v.fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)(kMaxLds - kStaticLdsReserve)) != hipSuccess)
+        return ME_EUNSUPPORTED;
+    // The runtime's occupancy answer, bounded by the LDS each workgroup takes
+    // (the query can report 0 for windows above 64 KiB even after the limit
+    // was raised; the LDS bound is then what applies).
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, v.fn, v.threads, v.lds) != hipSuccess) per_cu = 0;
+    const int by_lds = (int)(kMaxLds / std::max<size_t>(v.lds, 1));
+    if (per_cu < 1) per_cu = std::min(by_lds, 2048 / v.threads);
+    if (per_cu < 1) return ME_EUNSUPPORTED;
+    *grid = (unsigned)(per_cu * cus);
+    return ME_OK;
+}
+
+int batch_launch(const me_job* jobs, int32_t n_jobs, int32_t algo, int32_t block, int32_t range, hipStream_t st) {
+    int kind = 0, rpl = 1, wpg = 1, tile_w = 1, tile_h = 1;
+    int rc = check_batch(jobs, n_jobs, algo, block, range, &kind, &rpl, &wpg, &tile_w, &tile_h);
+    if (rc != ME_OK) return rc;
 
     // Table contents (host side, before touching shared state).
     std::vector<BatchJob> tab;
@@ -184,21 +240,9 @@ int batch_launch(const me_job* jobs, int32_t n_jobs, int32_t algo, int32_t block
     for (int i = 0; i < n_jobs; ++i) {
         const me_job& j = jobs[i];
         if (j.n_pairs == 0) continue;
-        BatchJob b;
-        b.a = frame_args(j.cur, j.ref, j.width, j.height, j.pitch, j.pair_stride, block, range, tile_w, tile_h);
-        b.flags = dcds_flags(algo, j.cur, j.ref, j.width, j.pitch, j.pair_stride);
-        b.tile_begin = (int)total;
-        b.start = reinterpret_cast<const int16_t*>(j.start);
-        b.orient = j.orient;
-        b.mv = reinterpret_cast<int16_t*>(j.mv);
-        b.sad = j.sad;
-        b.nsp = j.nsp;
-        b.sse = j.sse;
-        total += (long long)b.a.tiles_x * b.a.tiles_y * j.n_pairs;
-        // The shared tile counter runs past the total by kBatchChunk for every
-        // workgroup before each has seen the end: 2^30 keeps it far from
-        // int overflow.
-        if (total > (1 << 30)) return ME_EUNSUPPORTED;
+        const BatchJob b = make_job(j, algo, block, range, tile_w, tile_h, total);
+        total += job_tiles(b, j.n_pairs);
+        if (total > kMaxTiles) return ME_EUNSUPPORTED;
         tab.push_back(b);
     }
     if (tab.empty()) return ME_OK;
@@ -207,7 +251,7 @@ int batch_launch(const me_job* jobs, int32_t n_jobs, int32_t algo, int32_t block
     if (v.lds > kMaxLds - kStaticLdsReserve) return ME_EUNSUPPORTED;
 
     std::lock_guard<std::mutex> lock(g_batch.mu);
-    int rc = ensure_state();
+    rc = ensure_state();
     if (rc != ME_OK) return rc;
     Slot& s = g_batch.slots[g_batch.next];
     g_batch.next = (g_batch.next + 1) % kSlots;
@@ -223,20 +267,9 @@ int batch_launch(const me_job* jobs, int32_t n_jobs, int32_t algo, int32_t block
     while (cap < (int)tab.size()) cap *= 2;
     const size_t table_bytes = batch_table_bytes(cap);
 
-    // The persistent kernels also hold a little static LDS (the grabbed tile
-    // index): their dynamic limit leaves room for it.
-    if (v.lds > 65536 && hipFuncSetAttribute(v.fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             (int)(kMaxLds - kStaticLdsReserve)) != hipSuccess)
-        return ME_EUNSUPPORTED;
-    // Workgroups resident per CU: the runtime's occupancy answer, bounded by
-    // the LDS each one takes (the query can report 0 for windows above 64 KiB
-    // even after the limit was raised; the LDS bound is then what applies).
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, v.fn, v.threads, v.lds) != hipSuccess) per_cu = 0;
-    const int by_lds = (int)(kMaxLds / std::max<size_t>(v.lds, 1));
-    if (per_cu < 1) per_cu = std::min(by_lds, 2048 / v.threads);
-    if (per_cu < 1) return ME_EUNSUPPORTED;
-    const unsigned grid = (unsigned)(per_cu * g_batch.cus);
+    unsigned grid = 0;
+    rc = persistent_grid(v, g_batch.cus, &grid);
+    if (rc != ME_OK) return rc;
 
     const GraphKey key{kind, block, rpl, wpg, range_class(range), v.fn, v.threads, v.lds, cap};
     auto it = s.graphs.find(key);
@@ -280,6 +313,136 @@ int device_identity(std::string* arch, int* runtime) {
 
 ME_EXPORT int me_batch(const me_job* jobs, int32_t n_jobs, int32_t algo, int32_t block, int32_t range, void* stream) {
     return batch_launch(jobs, n_jobs, algo, block, range, reinterpret_cast<hipStream_t>(stream));
+}
+
+// ---------------------------------------------------------------------------
+// me_batch_noalloc: the same persistent launch with its job table and tile
+// counter in a file-scope device array instead of library allocations.  The
+// table reaches the array through the arguments of small copy kernels (16
+// jobs each), so the call needs no pinned buffer, no device allocation and no
+// host-to-device copy of pageable memory; a header kernel then writes the job
+// count and total and resets the counter (a kernel, not a memset), and the
+// persistent kernel reads them in stream order.  Each device holds its own
+// copy of the array; its address comes from hipGetSymbolAddress on the first
+// call on that device.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kNoAllocJobs = 512;
+constexpr size_t kScratchHead = 256;  // the tile counter, alone in its cache line
+constexpr size_t kScratchBytes = kScratchHead + batch_table_bytes(kNoAllocJobs);
+
+}  // namespace
+
+// Job table and tile counter of me_batch_noalloc (one copy per device).
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kChunkJobs = 16;
+struct JobChunk {
+    BatchJob jobs[kChunkJobs];  // 2 KiB of kernel arguments
+};
+static_assert(sizeof(BatchJob) % 4 == 0, "jobs are copied as 32-bit words");
+
+__global__ __launch_bounds__(256) void k_table_write(JobChunk c, BatchTable* __restrict__ tab, int first, int n) {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(c.jobs);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&tab->jobs[first]);
+    const int words = n * (int)(sizeof(BatchJob) / 4);
+    for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+}
+
+__global__ void k_table_head(BatchTable* __restrict__ tab, int* __restrict__ counter, int n_jobs, int total) {
+    if (threadIdx.x == 0) {
+        tab->n_jobs = n_jobs;
+        tab->total_tiles = total;
+        counter[0] = 0;
+    }
+}
+
+constexpr int kMaxDevices = 64;
+struct ScratchOfDevice {
+    std::atomic<bool> ready{false};
+    unsigned char* ptr = nullptr;  // device address of this device's copy of `scratch`
+    int cus = 0;
+};
+ScratchOfDevice g_scratch[kMaxDevices];
+std::mutex g_scratch_mu;
+
+// This device's copy of the array and its CU count (set up once per device,
+// with that device current).
+int scratch_of_device(unsigned char** ptr, int* cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return ME_EDEVICE;
+    if (dev < 0 || dev >= kMaxDevices) return ME_EUNSUPPORTED;
+    ScratchOfDevice& d = g_scratch[dev];
+    if (!d.ready.load(std::memory_order_acquire)) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!d.ready.load(std::memory_order_relaxed)) {
+            void* p = nullptr;
+            if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return ME_EDEVICE;
+            int n = 0;
+            if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1)
+                return ME_EDEVICE;
+            d.ptr = static_cast<unsigned char*>(p);
+            d.cus = n;
+            d.ready.store(true, std::memory_order_release);
+        }
+    }
+    *ptr = d.ptr;
+    *cus = d.cus;
+    return ME_OK;
+}
+
+}  // namespace
+
+ME_EXPORT int me_batch_noalloc(const me_job* jobs, int32_t n_jobs, int32_t algo, int32_t block, int32_t range,
+                               void* stream) {
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    int kind = 0, rpl = 1, wpg = 1, tile_w = 1, tile_h = 1;
+    int rc = check_batch(jobs, n_jobs, algo, block, range, &kind, &rpl, &wpg, &tile_w, &tile_h);
+    if (rc != ME_OK) return rc;
+    if (n_jobs > kNoAllocJobs) return ME_EUNSUPPORTED;
+    long long total = 0;
+    int n = 0;
+    for (int i = 0; i < n_jobs; ++i) {
+        if (jobs[i].n_pairs == 0) continue;
+        total += job_tiles(make_job(jobs[i], algo, block, range, tile_w, tile_h, 0), jobs[i].n_pairs);
+        if (total > kMaxTiles) return ME_EUNSUPPORTED;
+        ++n;
+    }
+    if (n == 0) return ME_OK;
+    const Variant v = pick_variant(kind, block, rpl, wpg, range);
+    if (v.lds > kMaxLds - kStaticLdsReserve) return ME_EUNSUPPORTED;
+    unsigned char* base = nullptr;
+    int cus = 0;
+    rc = scratch_of_device(&base, &cus);
+    if (rc != ME_OK) return rc;
+    unsigned grid = 0;
+    rc = persistent_grid(v, cus, &grid);
+    if (rc != ME_OK) return rc;
+
+    int* counter = reinterpret_cast<int*>(base);
+    BatchTable* tab = reinterpret_cast<BatchTable*>(base + kScratchHead);
+    JobChunk chunk;
+    int in_chunk = 0, first = 0;
+    long long begin = 0;
+    for (int i = 0; i < n_jobs; ++i) {
+        if (jobs[i].n_pairs == 0) continue;
+        chunk.jobs[in_chunk] = make_job(jobs[i], algo, block, range, tile_w, tile_h, begin);
+        begin += job_tiles(chunk.jobs[in_chunk], jobs[i].n_pairs);
+        if (++in_chunk == kChunkJobs || first + in_chunk == n) {
+            hipLaunchKernelGGL(k_table_write, dim3(1), dim3(256), 0, st, chunk, tab, first, in_chunk);
+            if (launched() != ME_OK) return ME_EDEVICE;  // no search over a partial table
+            first += in_chunk;
+            in_chunk = 0;
+        }
+    }
+    hipLaunchKernelGGL(k_table_head, dim3(1), dim3(64), 0, st, tab, counter, n, (int)total);
+    if (launched() != ME_OK) return ME_EDEVICE;
+    void* args[] = {&tab, &counter};
+    if (hipLaunchKernel(v.fn, dim3(grid), dim3(v.threads), args, v.lds, st) != hipSuccess) return ME_EDEVICE;
+    return launched();
 }
 
 // Records a tuning result, replacing an earlier one for the same device,
