@@ -119,6 +119,25 @@ def valu_issue_for(kernel: str, ms: float):
             "lanes_active": rec.get("lanes_active"), "source": rec.get("summary")}
 
 
+def fs_roofline(rates, achieved):
+    """Full search against the v_qsad_pk_u16_u8 issue peak.  The calibration
+    times the instructions in seconds and converts at 2.4 GHz; a plain
+    integer add (v_xad_u32) issues every 4 cycles per SIMD, so its reading
+    gives the clock the calibration actually ran at.  The peak is stated at
+    the 2.4 GHz peak clock: the qsad cost in true cycles (its reading times
+    4 / the add's), at 256 CUs x 4 SIMDs x 2.4 GHz, 1024 absolute differences
+    per wave instruction."""
+    cyc = rates["cycles_per_wave_instruction"]
+    measured_peak = rates["absdiff_per_s"]["v_qsad_pk_u16_u8"]
+    clock = 2.4 * 4.0 / cyc["v_xad_u32"]
+    qsad_cycles = cyc["v_qsad_pk_u16_u8"] * 4.0 / cyc["v_xad_u32"]
+    peak = rates["cus"] * 4 * 2.4e9 / qsad_cycles * 64 * 16
+    return {"achieved_absdiff_per_s": achieved, "peak_absdiff_per_s": peak, "frac": achieved / peak,
+            "peak_clock_ghz": 2.4, "qsad_cycles_per_wave_instruction": qsad_cycles,
+            "calibration_clock_ghz": clock, "peak_at_measured_clock": measured_peak,
+            "frac_at_measured_clock": achieved / measured_peak}
+
+
 _CPU_SEQ = None  # the sequence the forked oracle workers read
 
 
@@ -127,6 +146,26 @@ def _oracle_pairs(pairs):
     for p in pairs:
         oracle.dcds(_CPU_SEQ[p + 1], _CPU_SEQ[p], BLOCK, RANGE)
     return len(pairs) * (W // BLOCK) * (H // BLOCK)
+
+
+def _oracle_fs_pair(p):
+    import oracle
+    oracle.fullsearch(_CPU_SEQ[p + 1], _CPU_SEQ[p], BLOCK, RANGE)
+    return (W // BLOCK) * (H // BLOCK)
+
+
+def host_info():
+    """The host's logical CPU count, the CPUs this process may use, and the CPU model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "cpu_model": model}
 
 
 def cpu_baseline(seq, budget_s=6.0):
@@ -165,6 +204,17 @@ def cpu_baseline(seq, budget_s=6.0):
     fs_dt = time.perf_counter() - t0
     res["fs_single_core_value"] = (W // BLOCK) * (H // BLOCK) / fs_dt
     res["fs_sample"] = "FS on pair 0 only, one thread (%.1f s)" % fs_dt
+    # FS on every core at once: one pair per process (pairs 0 .. cores-1).
+    with ProcessPoolExecutor(max_workers=cores, mp_context=multiprocessing.get_context("fork")) as ex:
+        list(ex.map(_oracle_pairs, [[0]] * cores))  # start the workers
+        t0 = time.perf_counter()
+        nf = sum(ex.map(_oracle_fs_pair, range(cores)))
+        fsk_dt = time.perf_counter() - t0
+    res["fs_all_core_value"] = nf / fsk_dt
+    res["fs_all_core_sample"] = "FS on pairs 0..%d, one pair per process on %d cores (%.1f s)" % (
+        cores - 1, cores, fsk_dt)
+    res["host"] = host_info()
+    res["compiler"] = "gcc %s" % " ".join(oracle.CC_FLAGS)
     print("# cpu oracle: %.3g MB/s on %d cores, %.3g MB/s on one" % (res["value"], cores, res["single_core_value"]),
           file=sys.stderr, flush=True)
     return res
@@ -188,7 +238,6 @@ def batch_leg(me, torch, dev, args):
     for k in range(4):
         order = [(i + 16 * k) % 64 for i in range(64)]
         tables.append(me.make_jobs([pairs[i] for i in order], 16))
-    outs = tables[0][1]
     stream = torch.cuda.current_stream().cuda_stream
     turn = [0]
 
@@ -198,16 +247,30 @@ def batch_leg(me, torch, dev, args):
         rc = me.me_batch(jobs, 64, me.ME_ALGO_DCDS, 16, RANGE, stream)
         assert rc == 0, rc
 
+    single = [me.dcds(c, r, 16, RANGE) for (c, r) in pairs]  # the per-stream calls' own outputs
+
     def per_stream():
-        for (c, r), o in zip(pairs, outs):
+        for (c, r), o in zip(pairs, single):
             me.dcds(c, r, 16, RANGE, out=o)
 
     steps = max(4, min(args.steps, 20))
     _, ms_batch, _ = time_launches(launch, steps, args.warmup, torch)
     _, ms_loop, _ = time_launches(per_stream, steps, args.warmup, torch)
+    # Every table's outputs, written by its last launch, against the
+    # per-stream calls, element by element.
+    for k in range(4):
+        launch_k = tables[k][0]
+        assert me.me_batch(launch_k, 64, me.ME_ALGO_DCDS, 16, RANGE, stream) == 0
+    torch.cuda.synchronize()
+    for k in range(4):
+        for i, o in enumerate(tables[k][1]):
+            ref_o = single[(i + 16 * k) % 64]
+            if not all(torch.equal(x, y) for x, y in zip(o, ref_o)):
+                raise AssertionError("batch table %d job %d differs from its per-stream call" % (k, i))
     me.me_set_config(16, RANGE, None)  # the other legs keep the built-in layout
-    nsp = sum(float(o[2].double().sum()) for o in outs) / blocks
+    nsp = sum(float(o[2].double().sum()) for o in tables[0][1]) / blocks
     res = {"streams": 64, "frames": 30, "blocks_per_launch": blocks, "ms_per_launch": ms_batch,
+           "checked": "all 4 tables x 64 jobs equal to the per-stream calls, element by element",
            "mb_per_s": blocks / (ms_batch * 1e-3), "per_stream_calls_ms": ms_loop,
            "per_stream_calls_mb_per_s": blocks / (ms_loop * 1e-3), "nsp_mean": nsp,
            "tables": "4 rotations of the stream list, one per launch",
@@ -313,6 +376,69 @@ def mvp_leg(me, torch, cur, ref, steps, warmup):
     return out
 
 
+def e2e_leg(me, torch, seq_np, dev, args):
+    """The headline call end to end from host memory: the 60 frames copied
+    from pinned host memory to the GPU, the DCDS call, and its outputs copied
+    back, timed by the host clock around a synchronised step (the PCIe-
+    inclusive rate; the headline times the call on resident frames)."""
+    host = torch.from_numpy(seq_np).pin_memory()
+    seq = torch.empty(host.shape, dtype=torch.uint8, device=dev)
+    P, Hc, Wc = host.shape[0] - 1, host.shape[1], host.shape[2]
+    outs = [torch.empty((P, Hc // 16, Wc // 16, 2), dtype=torch.int16).pin_memory(),
+            torch.empty((P, Hc // 16, Wc // 16), dtype=torch.int32).pin_memory(),
+            torch.empty((P, Hc // 16, Wc // 16), dtype=torch.int32).pin_memory()]
+
+    def step():
+        seq.copy_(host, non_blocking=True)
+        res = me.dcds(seq[1:], seq[:-1], 16, RANGE)
+        for o, r in zip(outs, res):
+            o.copy_(r, non_blocking=True)
+        torch.cuda.synchronize()
+
+    for _ in range(3):
+        step()
+    n = max(5, min(args.steps, 20))
+    t0 = time.perf_counter()
+    for _ in range(n):
+        step()
+    ms = (time.perf_counter() - t0) * 1e3 / n
+    blocks = P * (Hc // 16) * (Wc // 16)
+    res = {"ms_per_step": ms, "mb_per_s": blocks / (ms * 1e-3), "bytes_h2d": int(host.numel()),
+           "bytes_d2h": sum(int(o.numel() * o.element_size()) for o in outs),
+           "what": "pinned host frames -> HBM, me_dcds over 59 pairs, outputs -> pinned host; host clock"}
+    print("# e2e: %.4f ms per step from host memory (%.3g MB/s)" % (ms, res["mb_per_s"]), file=sys.stderr,
+          flush=True)
+    return res
+
+
+def small_config_leg(me, torch, dev, k, args):
+    """Configs 1 (176x144, one pair) and 2 (352x288, 300 frames, 299 pairs), 16x16
+    blocks, +-7: FS, plain DCDS and learned-start DCDS, one launch per step
+    over every pair of the sequence."""
+    from synth import make_config
+    seq_np = make_config(k)
+    seq = torch.from_numpy(seq_np).to(dev)
+    cur, ref = seq[1:], seq[:-1]
+    R = 7
+    steps = max(5, min(args.steps, 50))
+    P, Hc, Wc = cur.shape
+    blocks = P * (Hc // 16) * (Wc // 16)
+    out = {"workload": "%dx%d uint8, %d frames (%d pairs), 16x16, +-%d, %d blocks per step" % (
+        Wc, Hc, P + 1, P, R, blocks)}
+    for name, fn in (("fs", lambda: me.fullsearch(cur, ref, 16, R)), ("dcds", lambda: me.dcds(cur, ref, 16, R))):
+        _, sad, nsp = fn()
+        _, ms, _ = time_launches(fn, steps, args.warmup, torch)
+        out[name] = {"mb_per_s": blocks / (ms * 1e-3), "ms_per_step": ms, "sad_mean": float(sad.double().mean()),
+                     "nsp_mean": float(nsp.double().mean())}
+    out["dcds"]["sad_over_fs"] = out["dcds"]["sad_mean"] / out["fs"]["sad_mean"]
+    out["dcds_learned"] = learned_leg(me, torch, cur, ref, R, steps, args.warmup, out["fs"]["sad_mean"],
+                                      out["dcds"])
+    print("# config%d: fs %.4f ms (%.3g MB/s), dcds %.4f ms (%.3g MB/s), sad/fs %.4f, nsp %.3f" % (
+        k, out["fs"]["ms_per_step"], out["fs"]["mb_per_s"], out["dcds"]["ms_per_step"], out["dcds"]["mb_per_s"],
+        out["dcds"]["sad_over_fs"], out["dcds"]["nsp_mean"]), file=sys.stderr, flush=True)
+    return out
+
+
 def config5_leg(me, torch, dev, args):
     """3840x2160, 60 frames, +-31, 16x16: plain DCDS, learned-start DCDS and FS."""
     from synth import make_config
@@ -348,7 +474,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only", default="",
-                    help="comma list of extra legs to run (fs,dcds8,dcds_s,learned,batch,quality,mvp,4k); "
+                    help="comma list of extra legs to run (fs,dcds8,fs8,dcds_s,learned,batch,quality,mvp,e2e,"
+                         "config1,config2,4k); "
                          "dcds always runs")
     ap.add_argument("--sweep", action="store_true",
                     help="time every DCDS kernel configuration (rows per lane x waves per group) and exit")
@@ -380,8 +507,8 @@ def main():
     seq = torch.from_numpy(seq_np).to(dev)
     cur, ref = seq[1:], seq[:-1]
     P = FRAMES - 1
-    legs = set(args.only.split(",")) if args.only else {"dcds", "fs", "dcds8", "dcds_s", "learned", "batch",
-                                                          "quality", "mvp", "4k"}
+    legs = set(args.only.split(",")) if args.only else {"dcds", "fs", "dcds8", "fs8", "dcds_s", "learned", "batch",
+                                                          "quality", "mvp", "e2e", "config1", "config2", "4k"}
     if args.calib_copy:
         src = torch.ones(256 << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -441,15 +568,18 @@ def main():
         fs = results["fs"]
         fs["valu_roofline"] = {"bound": "alu", "instr": "v_qsad_pk_u16_u8", "rates": rates}
         if "absdiff_per_s" in rates:
-            absd = fs["nsp_mean"] * 256 * blocks16 / (fs["ms_per_step"] * 1e-3)
-            peak = rates["absdiff_per_s"]["v_qsad_pk_u16_u8"]
-            fs["valu_roofline"].update({"achieved_absdiff_per_s": absd, "peak_absdiff_per_s": peak,
-                                        "frac": absd / peak})
-            print("# fs: %.3g absolute differences/s, %.0f%% of the measured v_qsad_pk_u16_u8 peak %.3g "
-                  "(%.1f cycles per wave instruction)" % (absd, 100 * absd / peak, peak,
-                  rates["cycles_per_wave_instruction"]["v_qsad_pk_u16_u8"]), file=sys.stderr, flush=True)
+            fs["valu_roofline"].update(fs_roofline(rates, fs["nsp_mean"] * 256 * blocks16 / (fs["ms_per_step"] * 1e-3)))
+            r = fs["valu_roofline"]
+            print("# fs: %.3g absolute differences/s, %.0f%% of the v_qsad_pk_u16_u8 peak at 2.4 GHz (%.3g), "
+                  "%.0f%% of the rate measured at the calibration's clock (%.2f GHz)" % (
+                      r["achieved_absdiff_per_s"], 100 * r["frac"], r["peak_absdiff_per_s"],
+                      100 * r["frac_at_measured_clock"], r["calibration_clock_ghz"]), file=sys.stderr, flush=True)
     if "dcds8" in legs:
         leg("dcds8", lambda: me.dcds(cur, ref, 8, RANGE), args.steps, blocks8)
+    if "fs8" in legs:
+        leg("fs8", lambda: me.fullsearch(cur, ref, 8, RANGE), max(3, min(args.steps, 10)), blocks8)
+        if "dcds8" in results:
+            results["dcds8"]["sad_over_fs"] = results["dcds8"]["sad_mean"] / results["fs8"]["sad_mean"]
     if "dcds_s" in legs:
         leg("dcds_s", lambda: me.dcds(cur, ref, 16, RANGE, algo=me.ME_ALGO_DCDS_S), args.steps, blocks16)
     if "learned" in legs:
@@ -463,6 +593,11 @@ def main():
         extra["quality"] = quality_leg(me, torch, cur, ref, RANGE, args.steps, args.warmup)
     if "mvp" in legs:
         extra["mvp_stats_r7"] = mvp_leg(me, torch, cur, ref, args.steps, args.warmup)
+    if "e2e" in legs:
+        extra["end_to_end"] = e2e_leg(me, torch, seq_np, dev, args)
+    for k in (1, 2):
+        if "config%d" % k in legs:
+            extra["config%d" % k] = small_config_leg(me, torch, dev, k, args)
     if "4k" in legs:
         del seq, cur, ref
         extra["config_4k_r31"] = config5_leg(me, torch, dev, args)
@@ -477,6 +612,8 @@ def main():
     d = results["dcds"]
     bytes_launch = BYTES_PER_BLOCK(16) * blocks16
     achieved = bytes_launch / (d["ms_per_step"] * 1e-3) / 1e9
+    traffic = traffic_for("k_dcds_1080p")
+    valu = valu_issue_for("k_dcds_1080p", d["ms_per_step"])
     line = {
         "metric": METRIC,
         "value": d["mb_per_s"],
@@ -506,9 +643,14 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "bytes_per_block": BYTES_PER_BLOCK(16),
-            "traffic": traffic_for("k_dcds_1080p"),
-            # What bounds the kernel in practice: its VALU issue rate.
-            "valu_issue": valu_issue_for("k_dcds_1080p", d["ms_per_step"]),
+            "traffic": traffic,
+            # HBM bytes the counters measured, over this run's launch time.
+            "traffic_gbs": traffic / (d["ms_per_step"] * 1e-3) / 1e9 if traffic else None,
+            "traffic_frac": traffic / (d["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS if traffic else None,
+            # What limits the kernel in practice: its VALU issue rate (the
+            # larger fraction of the two).
+            "valu_issue": valu,
+            "limiter": ("valu_issue" if valu and valu["frac"] > achieved / HBM_PEAK_GBS else "hbm"),
         },
         "cpu_baseline": None,
     }

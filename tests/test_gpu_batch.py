@@ -124,3 +124,40 @@ def test_shutdown_then_reuse(streams):
     b = me.batch(pairs, 16, 15)
     for x, y in zip(a, b):
         assert equal(x, y)
+
+
+def test_config4_scale_rotated_tables():
+    """The benchmarked batch at full size: 64 streams (16 each of 176x144,
+    352x288, 1280x720, 1920x1088), 30 frames, 16x16, +-15, 5.69 M blocks per
+    launch.  Four job tables (the stream list rotated by 16) replay one
+    captured graph; every job equals its single call element by element, and
+    one sampled pair per size class equals the oracle."""
+    from synth import batch_streams
+    seqs_np = batch_streams(64, 30)
+    seqs = [dev(s) for s in seqs_np]
+    pairs = [(s[1:], s[:-1]) for s in seqs]
+    single = [me.dcds(c, r, 16, 15) for c, r in pairs]
+    stream = torch.cuda.current_stream().cuda_stream
+    tables = []
+    for k in range(4):
+        order = [(i + 16 * k) % 64 for i in range(64)]
+        tables.append((order, me.make_jobs([pairs[i] for i in order], 16)))
+    for rep in range(2):  # two passes over the four tables
+        for k, (order, (jobs, outs)) in enumerate(tables):
+            say("case config4 pass %d table %d" % (rep, k))
+            for o in outs:
+                for x in o:
+                    x.fill_(-1)
+            assert me.me_batch(jobs, 64, me.ME_ALGO_DCDS, 16, 15, stream) == me.ME_OK
+            for i, o in zip(order, outs):
+                assert equal(o, single[i]), (rep, k, i)
+    rng = np.random.default_rng(44)
+    for kind in range(4):
+        s = kind + 4 * int(rng.integers(0, 16))
+        p = int(rng.integers(0, 29))
+        emv, esad, ensp = oracle.dcds(seqs_np[s][p + 1], seqs_np[s][p], 16, 15)
+        order, (jobs, outs) = tables[1]
+        g = outs[order.index(s)]
+        assert np.array_equal(g[0][p].cpu().numpy(), emv), (s, p)
+        assert np.array_equal(g[1][p].cpu().numpy(), esad.astype(np.int32)), (s, p)
+        assert np.array_equal(g[2][p].cpu().numpy(), ensp.astype(np.int32)), (s, p)
