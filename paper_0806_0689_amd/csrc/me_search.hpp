@@ -234,16 +234,27 @@ __device__ __forceinline__ WalkOut dcds_walk(const Ev& ev, int R, const Bounds& 
             r1 = d1 < d0;
         }
     }
+    // A middle point visited before cannot beat the centre (nor tie it: ties
+    // keep the centre), so only unvisited ones are evaluated, and the wave
+    // skips the evaluation when none of its searches has one.  Reading the
+    // bitmap after this group's marks is ordered (LDS operations of a wave
+    // complete in order).
     const int arm = t ? rs : 1;
-    {
-        const int ka = t ? S : 1;
-        mark_point(bm, (g == 0 && r0) || (g == 1 && r1), g == 0 ? kc - ka : kc + ka);
-    }
-    uint32_t mc0, mc1;
-    ev.pair(ca - arm, ca + arm, mc0, mc1);
+    const int ka = t ? S : 1;
+    const int k0 = max(kc - ka, 0), k1 = min(kc + ka, S * S - 1);  // in the bitmap even when not used
+    const bool n0 = r0 && !((bm[k0 >> 5] >> (k0 & 31)) & 1u);
+    const bool n1 = r1 && !((bm[k1 >> 5] >> (k1 & 31)) & 1u);
+    mark_point(bm, (g == 0 && n0) || (g == 1 && n1), g == 0 ? kc - ka : kc + ka);
     uint32_t mf = cc8;
-    mf = min(mf, key(r0, mc0, 1u));
-    mf = min(mf, key(r1, mc1, 2u));
+    if (__ballot(n0 && n1)) {
+        uint32_t mc0, mc1;
+        ev.pair(ca - arm, ca + arm, mc0, mc1);
+        mf = min(mf, key(n0, mc0, 1u));
+        mf = min(mf, key(n1, mc1, 2u));
+    } else if (__ballot(n0 || n1)) {
+        const uint32_t mc = ev.one(n0 ? ca - arm : ca + arm);
+        mf = min(mf, key(n0 || n1, mc, n0 ? 1u : 2u));
+    }
     const uint32_t wf = mf & 7u;
     if (wf != 0) {
         const int o = wf == 1 ? -1 : 1;

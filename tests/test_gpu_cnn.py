@@ -29,8 +29,8 @@ def frames():
     return seq
 
 
-def close(got, ref, what, rel):
-    """Elementwise |got - ref| <= rel * (|ref| + rms(ref)), and cosine > 1 - rel."""
+def close(got, ref, what, rel, cos_min):
+    """Elementwise |got - ref| <= rel * (|ref| + rms(ref)), and cosine >= cos_min."""
     got = np.asarray(got, np.float64).ravel()
     ref = np.asarray(ref, np.float64).ravel()
     rms = np.sqrt(np.mean(ref * ref)) + 1e-30
@@ -39,13 +39,18 @@ def close(got, ref, what, rel):
     cos = float(got @ ref / (np.linalg.norm(got) * np.linalg.norm(ref) + 1e-30))
     say("%s: worst scaled error %.3e, cosine %.9f" % (what, worst, cos))
     assert worst <= rel, (what, worst)
-    assert cos >= 1.0 - rel, (what, cos)
+    assert cos >= cos_min, (what, cos)
 
 
-# bf16 keeps 8 significant bits: one rounding flip moves an activation by
-# <= 2^-8 of itself; a few layers of such flips stay well inside 2^-5 of the
-# tensor's own scale, while fp32 summation-order effects are ~1e-6.
-REL = 2.0 ** -5
+# bf16 keeps 8 significant bits: one rounding flip moves a stored value by
+# <= 2^-8 of itself, while fp32 summation-order effects are ~1e-6 relative.
+# The head (fp32, read from bf16 layer-3 activations) is bounded by one flip
+# at its own scale.  Gradients sum products over many pixels, which dilutes
+# a flip far below that: they are bounded tighter.
+REL = 2.0 ** -8        # head and loss: elementwise, scaled
+COS = 1.0 - 2.0 ** -16  # head: cosine
+REL_G = 2.0 ** -12     # gradients: elementwise, scaled
+COS_G = 1.0 - 2.0 ** -20
 
 
 def test_forward_matches_oracle(frames):
@@ -57,7 +62,7 @@ def test_forward_matches_oracle(frames):
     for k in range(2):
         x0 = cnn.downdiff(cur[k], ref[k])
         h, _ = cnn.forward(x0, ps)
-        close(head[k], h, "head pair %d" % k, REL)
+        close(head[k], h, "head pair %d" % k, REL, COS)
 
 
 def test_backward_matches_oracle(frames):
@@ -77,8 +82,8 @@ def test_backward_matches_oracle(frames):
     at = 0
     for li, (ws, bs) in enumerate(shapes):
         nw, nb = int(np.prod(ws)), int(np.prod(bs))
-        close(g[at:at + nw], gref[at:at + nw], "dW layer %d" % (li + 1), REL)
-        close(g[at + nw:at + nw + nb], gref[at + nw:at + nw + nb], "db layer %d" % (li + 1), REL)
+        close(g[at:at + nw], gref[at:at + nw], "dW layer %d" % (li + 1), REL_G, COS_G)
+        close(g[at + nw:at + nw + nb], gref[at + nw:at + nw + nb], "db layer %d" % (li + 1), REL_G, COS_G)
         at += nw + nb
 
 
@@ -92,11 +97,21 @@ def test_train_step_loss_and_adam(frames):
     loss = float(p.train_step(dev(cur), dev(ref), dev(tgt), lr).cpu()[0])
     ps = cnn.unflatten(w0)
     heads = [cnn.forward(cnn.downdiff(cur[k], ref[k]), ps)[0] for k in range(2)]
-    lref, _ = cnn.loss_and_dhead(np.stack(heads), tgt)
+    lref, dhead = cnn.loss_and_dhead(np.stack(heads), tgt)
     say("loss gpu %.7f oracle %.7f" % (loss, lref))
     assert abs(loss - lref) <= REL * abs(lref)
-    # Adam's first step from zero moments on the GPU's own gradient.
+    # The gradient train_step built (loss gradient through both pairs)
+    # against the oracle's backward of the oracle's loss gradient.
     g = p.get_grads().astype(np.float64)
+    gref = sum(cnn.flatten(cnn.backward(cnn.forward(cnn.downdiff(cur[k], ref[k]), ps)[1], ps, dhead[k]))
+               for k in range(2))
+    at = 0
+    for li, (ws, bs) in enumerate(cnn.param_shapes()):
+        nw, nb = int(np.prod(ws)), int(np.prod(bs))
+        close(g[at:at + nw], gref[at:at + nw], "train dW layer %d" % (li + 1), REL_G, COS_G)
+        close(g[at + nw:at + nw + nb], gref[at + nw:at + nw + nb], "train db layer %d" % (li + 1), REL_G, COS_G)
+        at += nw + nb
+    # Adam's first step from zero moments on the GPU's own gradient.
     m = 0.1 * g
     v = 0.001 * g * g
     step = lr * (m / 0.1) / (np.sqrt(v / 0.001) + 1e-8)
