@@ -204,22 +204,26 @@ static pt dcds_from(search_state *st, pt start, int first_vertical, int variant,
 }
 
 /* Learned start (not part of the paper's method).  Plain DCDS runs first,
- * from the origin.  Then the proposed start s is probed; only if it beats
- * the plain result does DCDS run a second time, with its first cross (HCSP,
- * or its transpose when orient_v) centred at s, over the same set S: a point
- * already in S keeps its distortion and is not counted again.  Every point of
- * S is then worse than the second search's centre, so the result is never
- * worse than plain DCDS's.                                                  */
+ * from the origin; call its result p.  Then the proposed start s is probed;
+ * if it beats the origin, DCDS runs a second time, with its first cross
+ * (HCSP, or its transpose when orient_v) centred at s, over the same set S:
+ * a point already in S keeps its distortion and is not counted again.  The
+ * result is the better of the two searches' results (a tie keeps p), so it
+ * is never worse than plain DCDS's.                                          */
 static pt dcds_seeded(search_state *st, pt s, int orient_v, int variant, int64_t *bdm_out)
 {
-    int64_t dp, ds;
+    int64_t dp, ds, dq;
     pt origin = {0, 0};
     pt p = dcds_from(st, origin, 0, variant, &dp);
-    if (same_pt(s, origin) || !eval_point(st, s.dx, s.dy, &ds) || ds >= dp) {
-        *bdm_out = dp;
+    *bdm_out = dp;
+    if (same_pt(s, origin) || !eval_point(st, s.dx, s.dy, &ds) || ds >= st->bdm[widx(st, 0, 0)])
         return p;
+    pt q = dcds_from(st, s, orient_v, variant, &dq);
+    if (dq < dp) {
+        *bdm_out = dq;
+        return q;
     }
-    return dcds_from(st, s, orient_v, variant, bdm_out);
+    return p;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -2,16 +2,17 @@
 // kernel.  One group of L lanes runs one search; every value below is uniform
 // across the group, and different groups of a wave diverge freely (EXEC masks).
 //
-// Visited points never win.  The centre is the minimum of every point met so
-// far (it only moves to a point of strictly smaller distortion, and ties keep
-// the centre), so a point evaluated before cannot beat it.  Two consequences
-// are used below:
+// Visited points never win.  Within one search, the centre is the minimum of
+// every point that search has met (it only moves to a point of strictly
+// smaller distortion, and ties keep the centre), so a point it evaluated
+// before cannot beat it.  Consequences used below:
 //  - each small-diamond step evaluates only its three new points: the distant
 //    point behind the centre (on the side it came from) is always a point of
 //    the previous pattern;
-//  - the set S of visited points only serves to count distinct points (NSP):
-//    it is a bitmap in LDS, one bit per window point, set (without reading
-//    it back) for every valid point evaluated, and NSP is its popcount.
+//  - the set S of visited points serves to count distinct points (NSP): it
+//    is a bitmap in LDS, one bit per window point, set for every valid point
+//    evaluated, and NSP is its popcount; Step 4 of a search that has it to
+//    itself also skips the middle points already in it.
 // The DCDS^S rule of Step 4 compares the two distant points of the final
 // diamond, so the cost of the one behind the centre is carried along.
 //
@@ -79,6 +80,7 @@ __device__ __forceinline__ uint32_t key(bool valid, uint32_t cost, uint32_t idx)
 struct WalkOut {
     int x, y;
     uint32_t cost;
+    uint32_t c0;  // cost of the first cross's centre
 };
 
 // Sets bit k of the group's bitmap when act (fire and forget).
@@ -106,7 +108,9 @@ __device__ __forceinline__ uint32_t count_points(const uint32_t* bm, int g) {
 // transpose when t.  AT_ORIGIN: the paper's start, (0, 0) with HCSP (its
 // cross reads the centre row once).  Every point evaluated is marked in bm.
 // Returns the final vector and its cost; the caller counts the points.
-template <int L, bool SIMPLIFIED, bool AT_ORIGIN, class Ev>
+// SKIP_VISITED: bm holds only this search's points, so Step 4 may skip a
+// middle point already in it (a point met before never beats the centre).
+template <int L, bool SIMPLIFIED, bool AT_ORIGIN, bool SKIP_VISITED, class Ev>
 __device__ __forceinline__ WalkOut dcds_walk(const Ev& ev, int R, const Bounds& bd, uint32_t* bm, int g, int cx,
                                              int cy, bool t) {
     const int S = 2 * R + 1;      // bitmap row length
@@ -149,7 +153,7 @@ __device__ __forceinline__ WalkOut dcds_walk(const Ev& ev, int R, const Bounds& 
     m = min(m, key(pm1, c7[5], 5u));
     m = min(m, key(pp1, c7[6], 6u));
     const uint32_t w = m & 7u;
-    if (w == 0) return WalkOut{cx, cy, m >> 3};  // half-way stop
+    if (w == 0) return WalkOut{cx, cy, m >> 3, c7[0]};  // half-way stop
 
     // Move to the BMP.  Switching strategy one: a BMP along x selects the
     // horizontal diamond, otherwise the vertical one.  dir: the last move
@@ -234,16 +238,19 @@ __device__ __forceinline__ WalkOut dcds_walk(const Ev& ev, int R, const Bounds& 
             r1 = d1 < d0;
         }
     }
-    // A middle point visited before cannot beat the centre (nor tie it: ties
-    // keep the centre), so only unvisited ones are evaluated, and the wave
-    // skips the evaluation when none of its searches has one.  Reading the
-    // bitmap after this group's marks is ordered (LDS operations of a wave
-    // complete in order).
+    // A middle point this search visited before cannot beat the centre (nor
+    // tie it: ties keep the centre), so with SKIP_VISITED only unvisited ones
+    // are evaluated, and the wave skips the evaluation when none of its
+    // searches has one.  Reading the bitmap after this group's marks is
+    // ordered (LDS operations of a wave complete in order).
     const int arm = t ? rs : 1;
     const int ka = t ? S : 1;
-    const int k0 = max(kc - ka, 0), k1 = min(kc + ka, S * S - 1);  // in the bitmap even when not used
-    const bool n0 = r0 && !((bm[k0 >> 5] >> (k0 & 31)) & 1u);
-    const bool n1 = r1 && !((bm[k1 >> 5] >> (k1 & 31)) & 1u);
+    bool n0 = r0, n1 = r1;
+    if constexpr (SKIP_VISITED) {
+        const int k0 = max(kc - ka, 0), k1 = min(kc + ka, S * S - 1);  // in the bitmap even when not used
+        n0 = n0 && !((bm[k0 >> 5] >> (k0 & 31)) & 1u);
+        n1 = n1 && !((bm[k1 >> 5] >> (k1 & 31)) & 1u);
+    }
     mark_point(bm, (g == 0 && n0) || (g == 1 && n1), g == 0 ? kc - ka : kc + ka);
     uint32_t mf = cc8;
     if (__ballot(n0 && n1)) {
@@ -260,23 +267,25 @@ __device__ __forceinline__ WalkOut dcds_walk(const Ev& ev, int R, const Bounds& 
         const int o = wf == 1 ? -1 : 1;
         if (t) cy += o; else cx += o;
     }
-    return WalkOut{cx, cy, mf >> 3};
+    return WalkOut{cx, cy, mf >> 3, c7[0]};
 }
 
 // The search of one block.  SIMPLIFIED: Step 4 of DCDS^S.  SEEDED: learned
 // start (sx, sy, orient_v; this library's addition): plain DCDS runs first;
-// the start, clamped into the candidate set, is then probed, and only if it
-// beats the plain result does DCDS run again with its first cross centred
-// there (HCSP, or its transpose when orient_v).  Every point of the first
-// search costs at least the plain result, so none of them can win in the
-// second, and the result is never worse than plain DCDS's.  Points shared by
-// both searches are counted once (the bitmap is common).
+// the start, clamped into the candidate set, is then probed, and if it beats
+// the origin DCDS runs again with its first cross centred there (HCSP, or
+// its transpose when orient_v).  The better of the two results is kept (a
+// tie keeps plain DCDS's), so it is never worse than plain DCDS's.  Points
+// shared by both searches are counted once (the bitmap is common); the second
+// search may meet points of the first that beat its centre, so it evaluates
+// every point of its patterns but the one it came from, as plain DCDS does,
+// and its Step 4 skips nothing.
 // bm: the group's bitmap, bitmap_words(RMAX) words, all zero on entry.
 template <int L, int RMAX, bool SIMPLIFIED, bool SEEDED, class Ev>
 __device__ SearchOut dcds_search(const Ev& ev, int R, const Bounds& bd, uint32_t* bm, int g, int sx, int sy,
                                  bool orient_v) {
     static_assert(L == 4 || L == 8 || L == 16, "group of 4, 8 or 16 lanes");
-    WalkOut r = dcds_walk<L, SIMPLIFIED, true>(ev, R, bd, bm, g, 0, 0, false);
+    WalkOut r = dcds_walk<L, SIMPLIFIED, true, true>(ev, R, bd, bm, g, 0, 0, false);
     if constexpr (SEEDED) {
         sx = clampi(sx, bd.lox, bd.hix);
         sy = clampi(sy, bd.loy, bd.hiy);
@@ -284,7 +293,10 @@ __device__ SearchOut dcds_search(const Ev& ev, int R, const Bounds& bd, uint32_t
             const int S = 2 * R + 1;
             mark_point(bm, g == 0, R * S + R + __mul24(sy, S) + sx);
             const uint32_t ps = ev.one(ev.a00 + __mul24(sy, ev.row()) + sx);
-            if (ps < r.cost) r = dcds_walk<L, SIMPLIFIED, false>(ev, R, bd, bm, g, sx, sy, orient_v);
+            if (ps < r.c0) {
+                const WalkOut q = dcds_walk<L, SIMPLIFIED, false, false>(ev, R, bd, bm, g, sx, sy, orient_v);
+                if (q.cost < r.cost) r = q;
+            }
         }
     }
     return SearchOut{r.x, r.y, r.cost, count_points<L, RMAX>(bm, g)};

@@ -151,6 +151,21 @@ def train(args):
     return meta
 
 
+def evaluate_checkpoint(args):
+    """Held-out evaluation of a saved checkpoint (no training)."""
+    import torch
+    import paper_0806_0689_amd as me
+    dev = torch.device("cuda:0")
+    p = load_proposer(args.out)
+    if p is None:
+        raise SystemExit("no checkpoint at %s" % args.out)
+    held = [torch.from_numpy(s).to(dev) for s in
+            generate(range(args.eval_sequences), args.frames, held_out=True, workers=args.workers)]
+    res = evaluate(me, p, held, args.range)
+    print("held-out:", json.dumps(res), flush=True)
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--sequences", type=int, default=40)
@@ -165,7 +180,12 @@ def main(argv=None):
     ap.add_argument("--log-every", type=int, default=100)
     ap.add_argument("--resume", action="store_true")
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
-    train(ap.parse_args(argv))
+    ap.add_argument("--eval-only", action="store_true", help="evaluate the checkpoint at --out on held-out data")
+    args = ap.parse_args(argv)
+    if args.eval_only:
+        evaluate_checkpoint(args)
+    else:
+        train(args)
 
 
 if __name__ == "__main__":

@@ -100,8 +100,8 @@ def test_simplified_dcds_relations():
 
 def test_seeded_start_relations():
     """Learned start (not in the paper): a zero start is plain DCDS; a start that
-    does not beat plain DCDS's result leaves that result (plus its probe point);
-    a start that does is never worse than itself."""
+    does not beat the origin leaves plain DCDS's result (plus its probe point);
+    otherwise the result is never worse than plain DCDS's."""
     seq = make_config(2, frames=2)
     cur, ref = seq[1], seq[0]
     B, R = 16, 7
@@ -126,12 +126,12 @@ def test_seeded_start_relations():
             ys = np.nonzero(valid.any(axis=1))[0] - R
             s = (int(np.clip(start[j, i, 0], xs.min(), xs.max())), int(np.clip(start[j, i, 1], ys.min(), ys.max())))
             ds = cost[s[1] + R, s[0] + R]
-            if s == (0, 0) or ds >= sad[j, i]:
+            if s == (0, 0) or ds >= cost[R, R]:
                 _, _, _, S = oracle.dcds_surface(cost, valid, want_set=True)
                 assert tuple(m1[j, i]) == tuple(mv[j, i]) and s1[j, i] == sad[j, i]
                 assert n1[j, i] == nsp[j, i] + (0 if S[s[1] + R, s[0] + R] else 1)
             else:
-                assert s1[j, i] <= ds
+                assert s1[j, i] <= min(ds, sad[j, i]) and n1[j, i] >= nsp[j, i]
             # The surface entry clamps nothing: give it the clamped start.
             r = oracle.dcds_surface(cost, valid, start=s, orient_v=bool(orient[j, i]))
             assert r[0] == tuple(m1[j, i]) and r[1] == s1[j, i] and r[2] == n1[j, i]

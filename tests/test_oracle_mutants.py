@@ -45,10 +45,12 @@ MUTANTS = {
                              "        if (vn || vp) {\n            list[1] = (vn && vp ? sp < sn : vp) ? mid[1] : mid[0];"),
     # Learned start: the proposer's orientation ignored (always HCSP).
     "seeded_vcsp_ignored": ("first_vertical ? VCSP : HCSP", "HCSP"),
-    # Learned start: the start followed whenever it beats the origin.
-    "seeded_gate_origin": ("|| ds >= dp)", "|| ds >= st->bdm[widx(st, 0, 0)])"),
-    # Learned start: the start always followed (no fallback to plain DCDS).
-    "seeded_no_fallback": ("|| ds >= dp)", "|| 0)"),
+    # Learned start: the second search only when the start beats plain DCDS's result.
+    "seeded_gate_plain": ("|| ds >= st->bdm[widx(st, 0, 0)])", "|| ds >= dp)"),
+    # Learned start: the second search's result always kept (no fallback to plain DCDS).
+    "seeded_no_fallback": ("if (dq < dp) {", "if (1) {"),
+    # Learned start: a tie between the two searches goes to the seeded one.
+    "seeded_tie_to_start": ("if (dq < dp) {", "if (dq <= dp) {"),
 }
 
 

@@ -6,9 +6,9 @@
   distance to the true vector) fixes that DCDS^S must still end on the true
   vector at every position of the window, edges included.
 * Learned start (this library's addition, not the paper's): the seeded first
-  cross is HCSP or its transpose around the start, and the search from the
-  start is only taken when the start beats plain DCDS's own result, so the
-  result is never worse than plain DCDS.
+  cross is HCSP or its transpose around the start; the search from the start
+  runs when the start beats the origin, and the better of the two searches'
+  results is kept, so the result is never worse than plain DCDS.
 
 Each pin is a function that raises AssertionError; the mutant tests run them
 against oracles with one planted mistake.
@@ -147,21 +147,32 @@ def pin_seeded_switching():
 
 
 def pin_seeded_gate():
-    """The start is only followed when it beats plain DCDS's result, not merely
-    the origin: plain DCDS walks from the origin (100) to (2, 0) (10); the start
-    (-5, 5) costs 20, better than the origin but not than 10, so the result is
-    plain DCDS's, with the start's probe counted once."""
+    """The second search runs when the start beats the origin, and the result
+    is the better of the two searches (a tie keeps plain DCDS's).  Plain DCDS
+    walks from the origin (100) to (2, 0) (10) with 11 points: the cross, the
+    diamond's (4, 0), (2, +-1) and the middle point (3, 0).  The start
+    s = (-5, 5) costs 20: better than the origin, not than 10.  From s the
+    second search moves to (-4, 5) and stops there (6 new cross points, 3 new
+    diamond points, both middle points already in S), so both searches and the
+    probe make 21 points.  With (-4, 5) at 3 the second search wins (a rule
+    that only follows starts better than plain DCDS's result would miss it);
+    at 15, and at 10 (a tie), plain DCDS's result stays.  A start worse than
+    the origin (120) runs no second search: 11 points plus the probe."""
     R, s = 7, (-5, 5)
-    c = surface(R, {(0, 0): 100, (2, 0): 10, s: 20})
-    plain = oracle.dcds_surface(c)
-    mv, d, nsp = oracle.dcds_surface(c, start=s, orient_v=False)
-    assert plain[:2] == ((2, 0), 10)
-    assert (mv, d, nsp) == (plain[0], plain[1], plain[2] + 1)
+    for v, want in ((3, ((-4, 5), 3, 21)), (15, ((2, 0), 10, 21)), (10, ((2, 0), 10, 21))):
+        c = surface(R, {(0, 0): 100, (2, 0): 10, s: 20, (-4, 5): v})
+        plain = oracle.dcds_surface(c)
+        assert plain == ((2, 0), 10, 11), plain
+        got = oracle.dcds_surface(c, start=s, orient_v=False)
+        assert got == want, (v, got)
+    c = surface(R, {(0, 0): 100, (2, 0): 10, s: 120, (-4, 5): 3})
+    assert oracle.dcds_surface(c, start=s, orient_v=False) == ((2, 0), 10, 12)
 
 
 def pin_seeded_never_worse():
     """On random surfaces and starts the learned-start result is never worse
-    than plain DCDS, and equals it whenever the start does not beat it."""
+    than plain DCDS, and equals it (plus the probe) whenever the start does not
+    beat the origin."""
     rng = np.random.default_rng(31)
     for R in (3, 7):
         n = 2 * R + 1
@@ -171,8 +182,8 @@ def pin_seeded_never_worse():
             v = bool(rng.integers(0, 2))
             p = oracle.dcds_surface(c, want_set=True)
             r = oracle.dcds_surface(c, start=s, orient_v=v)
-            assert r[1] <= p[1]
-            if s == (0, 0) or c[s[1] + R, s[0] + R] >= p[1]:
+            assert r[1] <= p[1] and r[2] >= p[2]
+            if s == (0, 0) or c[s[1] + R, s[0] + R] >= c[R, R]:
                 assert r[:2] == p[:2] and r[2] == p[2] + (0 if p[3][s[1] + R, s[0] + R] else 1)
 
 
