@@ -274,7 +274,8 @@ def batch_leg(me, torch, dev, args):
            "mb_per_s": blocks / (ms_batch * 1e-3), "per_stream_calls_ms": ms_loop,
            "per_stream_calls_mb_per_s": blocks / (ms_loop * 1e-3), "nsp_mean": nsp,
            "tables": "4 rotations of the stream list, one per launch",
-           "config": {"rows_per_lane": cfg[0], "waves_per_group": cfg[1], "source": "me_autotune",
+           "config": {"rows_per_lane": cfg[0], "waves_per_group": cfg[1], "tiles_per_grab": cfg[2],
+                      "source": "me_autotune",
                       "autotune_ms": tune_ms}}
     print("# batch: %.4f ms per launch (%.3g MB/s), autotuned %s; 64 separate calls %.4f ms" % (
         ms_batch, res["mb_per_s"], cfg, ms_loop), file=sys.stderr, flush=True)
@@ -636,7 +637,7 @@ def main():
         "algos": results,
         **extra,
         "roofline": {
-            "kernel": "k_dcds<16,%d,%d,15>" % me.me_get_config(16, RANGE),
+            "kernel": "k_dcds<16,%d,%d,15>" % me.me_get_config(16, RANGE)[:2],
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

@@ -81,20 +81,24 @@ enum {
 const char *me_status_string(int status);
 
 /*
- * Kernel configuration of the DCDS searches (me_dcds, me_dcds_ex): how many
- * rows of a block one lane holds (1, 2 or 4 for 16x16 blocks; 1 or 2 for 8x8)
- * and how many waves share one staged reference window (1, 2, 4 or 8; each wave
- * takes 64 * rows_per_lane / block blocks side by side).  Results do not
+ * Kernel configuration of the DCDS searches (me_dcds, me_dcds_ex, me_batch):
+ * how many rows of a block one lane holds (1, 2 or 4 for 16x16 blocks; 1 or 2
+ * for 8x8), how many waves share one staged reference window (1, 2, 4 or 8;
+ * each wave takes 64 * rows_per_lane / block blocks side by side) and, for the
+ * batched launches, how many work tiles a workgroup takes per grab from the
+ * shared counter (1, 2, 4, 8 or 16; 0 = the default, 4).  Results do not
  * depend on it, only speed.  Kept per block size and range class (1-7, 8-15,
  * 16-31) for the process; me_set_config with cfg == NULL restores the
  * built-in default; ME_EUNSUPPORTED for values outside the lists (and, at call
  * time, for a configuration whose window exceeds the 160 KiB of LDS of a
- * compute unit).  Not meant to
- * change while searches of that class are being enqueued from another thread.
+ * compute unit).  me_get_config reports the values in force (tiles_per_grab
+ * never 0).  Not meant to change while searches of that class are being
+ * enqueued from another thread.
  */
 typedef struct {
     int32_t rows_per_lane;
     int32_t waves_per_group;
+    int32_t tiles_per_grab;
 } me_config;
 
 int me_set_config(int32_t block, int32_t range, const me_config *cfg);
@@ -276,10 +280,12 @@ int me_batch(const me_job *jobs, int32_t n_jobs, int32_t algo, int32_t block, in
 int me_batch_noalloc(const me_job *jobs, int32_t n_jobs, int32_t algo, int32_t block, int32_t range, void *stream);
 
 /*
- * Autotuner: times every DCDS kernel configuration (me_config) on the given
- * batch with `reps` launches each (me_batch on `stream`, synchronising it),
- * keeps the fastest for (block, range class) via me_set_config, and returns it
- * with its time per launch in milliseconds (best, best_ms may be NULL).
+ * Autotuner: times every DCDS kernel layout (rows_per_lane x waves_per_group)
+ * on the given batch with `reps` launches each (me_batch on `stream`,
+ * synchronising it), then every tiles_per_grab with the fastest layout,
+ * keeps the fastest configuration for (block, range class) via me_set_config,
+ * and returns it with its time per launch in milliseconds (best, best_ms may
+ * be NULL).
  * algo: ME_ALGO_DCDS or ME_ALGO_DCDS_S.  Outputs of the jobs are overwritten.
  *
  * me_autotune_save writes every result of this process (and every entry

@@ -68,7 +68,8 @@ MAX_JOBS = 4096
 
 
 class MeConfig(ctypes.Structure):
-    _fields_ = [("rows_per_lane", ctypes.c_int32), ("waves_per_group", ctypes.c_int32)]
+    _fields_ = [("rows_per_lane", ctypes.c_int32), ("waves_per_group", ctypes.c_int32),
+                ("tiles_per_grab", ctypes.c_int32)]
 
 
 class MeJob(ctypes.Structure):
@@ -223,16 +224,19 @@ def me_dcds_surface(cost, valid, n, range_, algo, start, orient, mv, cost_out, n
 
 
 def me_set_config(block, range_, cfg):
-    """cfg: (rows_per_lane, waves_per_group) or None for the default."""
-    p = None if cfg is None else ctypes.byref(MeConfig(int(cfg[0]), int(cfg[1])))
+    """cfg: (rows_per_lane, waves_per_group[, tiles_per_grab]) or None for the
+    default; a missing or 0 tiles_per_grab means the default grab."""
+    p = None if cfg is None else ctypes.byref(MeConfig(int(cfg[0]), int(cfg[1]),
+                                                       int(cfg[2]) if len(cfg) > 2 else 0))
     return lib().me_set_config(block, range_, p)
 
 
 def me_get_config(block, range_):
+    """(rows_per_lane, waves_per_group, tiles_per_grab) in force."""
     c = MeConfig()
     rc = lib().me_get_config(block, range_, ctypes.byref(c))
     _check(rc, "me_get_config")
-    return c.rows_per_lane, c.waves_per_group
+    return c.rows_per_lane, c.waves_per_group, c.tiles_per_grab
 
 
 def me_batch(jobs, n_jobs, algo, block, range_, stream=0):
@@ -246,11 +250,11 @@ def me_batch_noalloc(jobs, n_jobs, algo, block, range_, stream=0):
 
 
 def me_autotune(jobs, n_jobs, algo, block, range_, reps, stream=0):
-    """Returns (status, (rows_per_lane, waves_per_group), ms)."""
+    """Returns (status, (rows_per_lane, waves_per_group, tiles_per_grab), ms)."""
     best = MeConfig()
     ms = ctypes.c_float(0.0)
     rc = lib().me_autotune(jobs, n_jobs, algo, block, range_, reps, ctypes.byref(best), ctypes.byref(ms), stream)
-    return rc, (best.rows_per_lane, best.waves_per_group), ms.value
+    return rc, (best.rows_per_lane, best.waves_per_group, best.tiles_per_grab), ms.value
 
 
 def me_autotune_save(path):

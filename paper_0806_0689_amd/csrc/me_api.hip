@@ -73,7 +73,9 @@ int pairs_per_launch(long long items_per_pair) {
 // ---------------------------------------------------------------------------
 int range_class(int R) { return R <= 7 ? 0 : (R <= 15 ? 1 : 2); }
 
-std::atomic<int> g_cfg[2][3];  // [block 8/16][range class] = rpl * 16 + wpg; 0 = default
+// [block 8/16][range class] = grab << 8 | rpl << 4 | wpg; a zero layout
+// (low byte) means the built-in layout, a zero grab the default grab.
+std::atomic<int> g_cfg[2][3];
 // Built-in defaults (rows per lane * 16 + waves per group) per block size and
 // range class (1-7, 8-15, 16-31): the fastest measured on MI355X over a
 // 1920x1088 sequence (59 pairs) at ranges 7, 15 and 31.
@@ -85,11 +87,16 @@ int default_cfg(int block, int rc) {
     return kDefault[block == 16][rc];
 }
 void current_cfg(int block, int rc, int* rpl, int* wpg) {
-    int v = g_cfg[block == 16][rc].load(std::memory_order_relaxed);
+    int v = g_cfg[block == 16][rc].load(std::memory_order_relaxed) & 255;
     if (!v) v = default_cfg(block, rc);
     *rpl = v / 16;
     *wpg = v % 16;
 }
+int current_grab(int block, int rc) {
+    const int g = g_cfg[block == 16][rc].load(std::memory_order_relaxed) >> 8;
+    return g ? g : kDefaultGrab;
+}
+bool valid_grab(int grab) { return grab == 0 || grab == 1 || grab == 2 || grab == 4 || grab == 8 || grab == 16; }
 bool valid_cfg(int block, int rpl, int wpg) {
     const bool r_ok = block == 16 ? (rpl == 1 || rpl == 2 || rpl == 4) : (rpl == 1 || rpl == 2);
     return r_ok && (wpg == 1 || wpg == 2 || wpg == 4 || wpg == 8);
@@ -204,8 +211,9 @@ ME_EXPORT int me_set_config(int32_t block, int32_t range, const me_config* cfg) 
         g_cfg[block == 16][rc].store(0);
         return ME_OK;
     }
-    if (!valid_cfg(block, cfg->rows_per_lane, cfg->waves_per_group)) return ME_EUNSUPPORTED;
-    g_cfg[block == 16][rc].store(cfg->rows_per_lane * 16 + cfg->waves_per_group);
+    if (!valid_cfg(block, cfg->rows_per_lane, cfg->waves_per_group) || !valid_grab(cfg->tiles_per_grab))
+        return ME_EUNSUPPORTED;
+    g_cfg[block == 16][rc].store(cfg->tiles_per_grab << 8 | cfg->rows_per_lane << 4 | cfg->waves_per_group);
     return ME_OK;
 }
 
@@ -217,6 +225,7 @@ ME_EXPORT int me_get_config(int32_t block, int32_t range, me_config* cfg) {
     current_cfg(block, range_class(range), &rpl, &wpg);
     cfg->rows_per_lane = rpl;
     cfg->waves_per_group = wpg;
+    cfg->tiles_per_grab = current_grab(block, range_class(range));
     return ME_OK;
 }
 

@@ -61,7 +61,7 @@ BatchState g_batch;
 struct TuneEntry {
     std::string arch;
     int runtime;
-    int block, rclass, rpl, wpg;
+    int block, rclass, rpl, wpg, grab;
     float ms;
 };
 std::mutex g_tune_mu;
@@ -161,9 +161,9 @@ int enqueue(Slot& s, const Variant& v, unsigned grid, size_t table_bytes, hipStr
 
 // Argument checks shared by me_batch and me_batch_noalloc (nothing is
 // launched on an error).  Returns the kernel kind, its configuration (rows
-// per lane, waves per group) and the tile shape in blocks.
+// per lane, waves per group, tiles per grab) and the tile shape in blocks.
 int check_batch(const me_job* jobs, int32_t n_jobs, int32_t algo, int32_t block, int32_t range, int* kind,
-                int* rpl, int* wpg, int* tile_w, int* tile_h) {
+                int* rpl, int* wpg, int* grab, int* tile_w, int* tile_h) {
     if (n_jobs < 0 || n_jobs > kMaxJobs) return ME_EINVAL;
     if (algo != ME_ALGO_FS && algo != ME_ALGO_DCDS && algo != ME_ALGO_DCDS_S) return ME_EUNSUPPORTED;
     if (block != 8 && block != 16) return ME_EUNSUPPORTED;
@@ -180,7 +180,11 @@ int check_batch(const me_job* jobs, int32_t n_jobs, int32_t algo, int32_t block,
     *kind = algo == ME_ALGO_FS ? KIND_FS : KIND_DCDS;
     *rpl = 1;
     *wpg = 1;
-    if (*kind == KIND_DCDS) current_cfg(block, range_class(range), rpl, wpg);
+    *grab = kDefaultGrab;
+    if (*kind == KIND_DCDS) {
+        current_cfg(block, range_class(range), rpl, wpg);
+        *grab = current_grab(block, range_class(range));
+    }
     *tile_w = *kind == KIND_FS ? 1 : 64 * *rpl / block;
     *tile_h = *kind == KIND_FS ? 1 : *wpg;
     return ME_OK;
@@ -204,9 +208,9 @@ BatchJob make_job(const me_job& j, int32_t algo, int32_t block, int32_t range, i
 
 long long job_tiles(const BatchJob& b, int n_pairs) { return (long long)b.a.tiles_x * b.a.tiles_y * n_pairs; }
 
-// The shared tile counter runs past the total by kBatchChunk for every
-// workgroup before each has seen the end: 2^30 keeps it far from int
-// overflow.
+// The shared tile counter runs past the total by one grab (at most
+// kMaxGrab tiles) for every workgroup before each has seen the end: 2^30
+// keeps it far from int overflow.
 constexpr long long kMaxTiles = 1LL << 30;
 
 // Grid of a persistent kernel: resident workgroups per CU x CUs.  The
@@ -229,8 +233,8 @@ int persistent_grid(const Variant& v, int cus, unsigned* grid) {
 }
 
 int batch_launch(const me_job* jobs, int32_t n_jobs, int32_t algo, int32_t block, int32_t range, hipStream_t st) {
-    int kind = 0, rpl = 1, wpg = 1, tile_w = 1, tile_h = 1;
-    int rc = check_batch(jobs, n_jobs, algo, block, range, &kind, &rpl, &wpg, &tile_w, &tile_h);
+    int kind = 0, rpl = 1, wpg = 1, grab = kDefaultGrab, tile_w = 1, tile_h = 1;
+    int rc = check_batch(jobs, n_jobs, algo, block, range, &kind, &rpl, &wpg, &grab, &tile_w, &tile_h);
     if (rc != ME_OK) return rc;
 
     // Table contents (host side, before touching shared state).
@@ -262,6 +266,7 @@ int batch_launch(const me_job* jobs, int32_t n_jobs, int32_t algo, int32_t block
 
     s.host->n_jobs = (int)tab.size();
     s.host->total_tiles = (int)total;
+    s.host->grab = grab;
     memcpy(s.host->jobs, tab.data(), tab.size() * sizeof(BatchJob));
     int cap = 64;
     while (cap < (int)tab.size()) cap *= 2;
@@ -352,10 +357,12 @@ __global__ __launch_bounds__(256) void k_table_write(JobChunk c, BatchTable* __r
     for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
 }
 
-__global__ void k_table_head(BatchTable* __restrict__ tab, int* __restrict__ counter, int n_jobs, int total) {
+__global__ void k_table_head(BatchTable* __restrict__ tab, int* __restrict__ counter, int n_jobs, int total,
+                             int grab) {
     if (threadIdx.x == 0) {
         tab->n_jobs = n_jobs;
         tab->total_tiles = total;
+        tab->grab = grab;
         counter[0] = 0;
     }
 }
@@ -399,8 +406,8 @@ int scratch_of_device(unsigned char** ptr, int* cus) {
 ME_EXPORT int me_batch_noalloc(const me_job* jobs, int32_t n_jobs, int32_t algo, int32_t block, int32_t range,
                                void* stream) {
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    int kind = 0, rpl = 1, wpg = 1, tile_w = 1, tile_h = 1;
-    int rc = check_batch(jobs, n_jobs, algo, block, range, &kind, &rpl, &wpg, &tile_w, &tile_h);
+    int kind = 0, rpl = 1, wpg = 1, grab = kDefaultGrab, tile_w = 1, tile_h = 1;
+    int rc = check_batch(jobs, n_jobs, algo, block, range, &kind, &rpl, &wpg, &grab, &tile_w, &tile_h);
     if (rc != ME_OK) return rc;
     if (n_jobs > kNoAllocJobs) return ME_EUNSUPPORTED;
     long long total = 0;
@@ -438,7 +445,7 @@ ME_EXPORT int me_batch_noalloc(const me_job* jobs, int32_t n_jobs, int32_t algo,
             in_chunk = 0;
         }
     }
-    hipLaunchKernelGGL(k_table_head, dim3(1), dim3(64), 0, st, tab, counter, n, (int)total);
+    hipLaunchKernelGGL(k_table_head, dim3(1), dim3(64), 0, st, tab, counter, n, (int)total, grab);
     if (launched() != ME_OK) return ME_EDEVICE;
     void* args[] = {&tab, &counter};
     if (hipLaunchKernel(v.fn, dim3(grid), dim3(v.threads), args, v.lds, st) != hipSuccess) return ME_EDEVICE;
@@ -473,32 +480,54 @@ ME_EXPORT int me_autotune(const me_job* jobs, int32_t n_jobs, int32_t algo, int3
     }
     me_config saved;
     me_get_config(block, range, &saved);
-    me_config top{0, 0};
+    me_config top{0, 0, 0};
     float top_ms = 0.f;
     int rc = ME_OK;
+    // Mean time per launch of configuration c over `reps` launches (after a
+    // warm-up that also builds the graph); ME_EUNSUPPORTED if c does not fit.
+    auto time_cfg = [&](const me_config& c, float* ms) -> int {
+        if (me_set_config(block, range, &c) != ME_OK) return ME_EUNSUPPORTED;
+        int r = batch_launch(jobs, n_jobs, algo, block, range, st);
+        if (r != ME_OK) return r;
+        if (hipEventRecord(e0, st) != hipSuccess) return ME_EDEVICE;
+        for (int i = 0; i < reps && r == ME_OK; ++i) r = batch_launch(jobs, n_jobs, algo, block, range, st);
+        if (r != ME_OK) return r;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return ME_EDEVICE;
+        if (hipEventElapsedTime(ms, e0, e1) != hipSuccess) return ME_EDEVICE;
+        *ms /= (float)reps;
+        return ME_OK;
+    };
+    // Every layout at the default grab, then every grab with the best layout.
     const int rpls[3] = {1, 2, 4};
     const int wpgs[4] = {1, 2, 4, 8};
     for (int ri = 0; ri < 3 && rc == ME_OK; ++ri) {
         for (int wi = 0; wi < 4 && rc == ME_OK; ++wi) {
-            me_config c{rpls[ri], wpgs[wi]};
-            if (me_set_config(block, range, &c) != ME_OK) continue;
-            int r = batch_launch(jobs, n_jobs, algo, block, range, st);  // warm-up, builds the graph
+            const me_config c{rpls[ri], wpgs[wi], kDefaultGrab};
+            float ms = 0.f;
+            const int r = time_cfg(c, &ms);
             if (r == ME_EUNSUPPORTED) continue;
             if (r != ME_OK) {
                 rc = r;
                 break;
             }
-            if (hipEventRecord(e0, st) != hipSuccess) rc = ME_EDEVICE;
-            for (int i = 0; i < reps && rc == ME_OK; ++i) rc = batch_launch(jobs, n_jobs, algo, block, range, st);
-            if (rc == ME_OK && hipEventRecord(e1, st) != hipSuccess) rc = ME_EDEVICE;
-            if (rc == ME_OK && hipEventSynchronize(e1) != hipSuccess) rc = ME_EDEVICE;
-            float ms = 0.f;
-            if (rc == ME_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = ME_EDEVICE;
-            ms /= (float)reps;
-            if (rc == ME_OK && (top.rows_per_lane == 0 || ms < top_ms)) {
+            if (top.rows_per_lane == 0 || ms < top_ms) {
                 top = c;
                 top_ms = ms;
             }
+        }
+    }
+    const int grabs[4] = {1, 2, 8, 16};
+    for (int gi = 0; gi < 4 && rc == ME_OK && top.rows_per_lane != 0; ++gi) {
+        const me_config c{top.rows_per_lane, top.waves_per_group, grabs[gi]};
+        float ms = 0.f;
+        const int r = time_cfg(c, &ms);
+        if (r != ME_OK) {
+            rc = r;
+            break;
+        }
+        if (ms < top_ms) {
+            top = c;
+            top_ms = ms;
         }
     }
     (void)hipEventDestroy(e0);
@@ -516,6 +545,7 @@ ME_EXPORT int me_autotune(const me_job* jobs, int32_t n_jobs, int32_t algo, int3
         e.rclass = range_class(range);
         e.rpl = top.rows_per_lane;
         e.wpg = top.waves_per_group;
+        e.grab = top.tiles_per_grab;
         e.ms = top_ms;
         remember(e);
     }
@@ -527,9 +557,11 @@ ME_EXPORT int me_autotune_save(const char* path) {
     FILE* f = fopen(path, "w");
     if (!f) return ME_EINVAL;
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    fprintf(f, "# me autotune cache v1: arch runtime block range_class rows_per_lane waves_per_group ms\n");
+    fprintf(f, "# me autotune cache v2: arch runtime block range_class rows_per_lane waves_per_group tiles_per_grab "
+               "ms\n");
     for (const auto& t : g_tune)
-        fprintf(f, "%s %d %d %d %d %d %.6f\n", t.arch.c_str(), t.runtime, t.block, t.rclass, t.rpl, t.wpg, t.ms);
+        fprintf(f, "%s %d %d %d %d %d %d %.6f\n", t.arch.c_str(), t.runtime, t.block, t.rclass, t.rpl, t.wpg, t.grab,
+                t.ms);
     const int bad = ferror(f);
     fclose(f);
     return bad ? ME_EINVAL : ME_OK;
@@ -548,20 +580,35 @@ ME_EXPORT int me_autotune_load(const char* path, int32_t* applied, int32_t* reje
     int n_ok = 0, n_bad = 0;
     while (fgets(line, sizeof line, f)) {
         if (line[0] == '#' || line[0] == '\n') continue;
+        // v2 lines carry tiles_per_grab before the time; v1 lines (without
+        // it) keep the default grab.
         char a[128];
-        int rt, blk, rcl, rpl, wpg;
+        int rt, blk, rcl, rpl, wpg, grab = kDefaultGrab;
         float ms;
-        if (sscanf(line, "%127s %d %d %d %d %d %f", a, &rt, &blk, &rcl, &rpl, &wpg, &ms) != 7 || rcl < 0 || rcl > 2 ||
-            (blk != 8 && blk != 16) || !valid_cfg(blk, rpl, wpg)) {
+        char extra[2];
+        int tokens = 0;
+        for (const char* q = line; *q;) {
+            while (*q == ' ' || *q == '\t' || *q == '\n' || *q == '\r') ++q;
+            if (!*q) break;
+            ++tokens;
+            while (*q && *q != ' ' && *q != '\t' && *q != '\n' && *q != '\r') ++q;
+        }
+        bool ok = false;
+        if (tokens == 8)
+            ok = sscanf(line, "%127s %d %d %d %d %d %d %f %1s", a, &rt, &blk, &rcl, &rpl, &wpg, &grab, &ms, extra) == 8;
+        else if (tokens == 7)
+            ok = sscanf(line, "%127s %d %d %d %d %d %f %1s", a, &rt, &blk, &rcl, &rpl, &wpg, &ms, extra) == 7;
+        if (!ok || rcl < 0 || rcl > 2 || (blk != 8 && blk != 16) || !valid_cfg(blk, rpl, wpg) || grab == 0 ||
+            !valid_grab(grab)) {
             ++n_bad;
             continue;
         }
         if (!have_id || arch != a || rt != runtime) continue;  // tuned on other hardware or runtime
         const int rep_range = rcl == 0 ? 7 : (rcl == 1 ? 15 : 31);
-        me_config c{rpl, wpg};
+        me_config c{rpl, wpg, grab};
         if (me_set_config(blk, rep_range, &c) == ME_OK) {
             ++n_ok;
-            remember(TuneEntry{a, rt, blk, rcl, rpl, wpg, ms});
+            remember(TuneEntry{a, rt, blk, rcl, rpl, wpg, grab, ms});
         }
     }
     fclose(f);

@@ -23,7 +23,8 @@ struct BatchJob {
 struct BatchTable {
     int n_jobs;
     int total_tiles;
-    int pad0, pad1;
+    int grab;  // tiles a workgroup takes per grab from the counter
+    int pad0;
     BatchJob jobs[1];  // n_jobs entries (the allocation holds the capacity)
 };
 
@@ -46,16 +47,16 @@ __device__ __forceinline__ int batch_job_of(const BatchTable* tab, int t) {
     return lo;
 }
 
-// Tiles are taken CHUNK at a time: one atomic and one job lookup serve
-// several tiles, which are then walked in order (crossing job boundaries with
-// one comparison each).
-constexpr int kBatchChunk = 4;
+// Tiles are taken `grab` at a time (the table's, 1 to 16): one atomic and
+// one job lookup serve several tiles, which are then walked in order
+// (crossing job boundaries with one comparison each).
+constexpr int kMaxGrab = 16;
 
 // Takes the next chunk for the whole workgroup; every wave leaves the previous
 // tile (and its LDS) before the new index is published.
-__device__ __forceinline__ int batch_next(int* counter, int* s_tile) {
+__device__ __forceinline__ int batch_next(int* counter, int grab, int* s_tile) {
     __syncthreads();
-    if (threadIdx.x == 0) *s_tile = atomicAdd(counter, kBatchChunk);
+    if (threadIdx.x == 0) *s_tile = atomicAdd(counter, grab);
     __syncthreads();
     return *s_tile;
 }
@@ -66,11 +67,12 @@ __global__ __launch_bounds__(64 * WPG) void k_dcds_batch(const BatchTable* __res
     __shared__ int s_tile;
     const int total = tab->total_tiles;
     const int n = tab->n_jobs;
+    const int grab = tab->grab;
     for (;;) {
-        const int t0 = batch_next(counter, &s_tile);
+        const int t0 = batch_next(counter, grab, &s_tile);
         if (t0 >= total) break;
         int j = batch_job_of(tab, t0);
-        const int t1 = min(t0 + kBatchChunk, total);
+        const int t1 = min(t0 + grab, total);
         for (int t = t0; t < t1; ++t) {
             while (j + 1 < n && tab->jobs[j + 1].tile_begin <= t) ++j;
             const BatchJob& jb = tab->jobs[j];
@@ -90,11 +92,12 @@ __global__ __launch_bounds__(256) void k_fs_batch(const BatchTable* __restrict__
     __shared__ int s_tile;
     const int total = tab->total_tiles;
     const int n = tab->n_jobs;
+    const int grab = tab->grab;
     for (;;) {
-        const int t0 = batch_next(counter, &s_tile);
+        const int t0 = batch_next(counter, grab, &s_tile);
         if (t0 >= total) break;
         int j = batch_job_of(tab, t0);
-        const int t1 = min(t0 + kBatchChunk, total);
+        const int t1 = min(t0 + grab, total);
         for (int t = t0; t < t1; ++t) {
             while (j + 1 < n && tab->jobs[j + 1].tile_begin <= t) ++j;
             const BatchJob& jb = tab->jobs[j];

@@ -24,7 +24,11 @@ FrameArgs frame_args(const uint8_t* cur, const uint8_t* ref, int32_t width, int3
 int range_class(int R);
 // rows per lane and waves per group of DCDS for (block, range class)
 void current_cfg(int block, int rc, int* rpl, int* wpg);
+// tiles per grab of the batched DCDS launches for (block, range class)
+int current_grab(int block, int rc);
 bool valid_cfg(int block, int rpl, int wpg);
+bool valid_grab(int grab);  // 0 (default), 1, 2, 4, 8 or 16
+constexpr int kDefaultGrab = 4;
 // DCDS flags for one job: simplified Step 4, 16-byte loads when aligned.
 int dcds_flags(int32_t algo, const uint8_t* cur, const uint8_t* ref, int32_t width, int32_t pitch,
                int64_t pair_stride);

@@ -157,9 +157,15 @@ def test_product_path_does_not_import_the_oracle():
 
 def test_config_set_get_and_checks():
     d16 = me.me_get_config(16, 15)
+    assert d16[2] == 4                              # default tiles per grab
     assert me.me_set_config(16, 15, (4, 2)) == me.ME_OK
-    assert me.me_get_config(16, 15) == (4, 2)
-    assert me.me_get_config(16, 9) == (4, 2)       # same range class 8..15
+    assert me.me_get_config(16, 15) == (4, 2, 4)
+    assert me.me_get_config(16, 9) == (4, 2, 4)    # same range class 8..15
+    assert me.me_set_config(16, 15, (4, 2, 16)) == me.ME_OK
+    assert me.me_get_config(16, 15) == (4, 2, 16)
+    assert me.me_set_config(16, 15, (4, 2, 3)) == me.ME_EUNSUPPORTED  # grabs: 1, 2, 4, 8, 16
+    assert me.me_set_config(16, 15, (4, 2, 32)) == me.ME_EUNSUPPORTED
+    assert me.me_get_config(16, 15) == (4, 2, 16)
     assert me.me_get_config(16, 7) == me.me_get_config(16, 1)
     assert me.me_set_config(16, 15, None) == me.ME_OK
     assert me.me_get_config(16, 15) == d16
@@ -208,12 +214,15 @@ def test_autotune_argument_checks(tmp_path):
     # Cache file: missing -> EINVAL (defaults stay); malformed lines are counted and skipped.
     assert me.me_autotune_load(str(tmp_path / "missing.txt"))[0] == me.ME_EINVAL
     f = tmp_path / "cache.txt"
+    # Lines of 7 fields (without tiles_per_grab) and of 8 fields are read.
     f.write_text("# header\nnot a line\ngfx950 70000000 16 1 3 4 0.1\ngfx950 70000000 16 9 2 4 0.1\n"
-                 "otherarch 1 16 1 2 4 0.5\n")
+                 "otherarch 1 16 1 2 4 0.5\n"
+                 "gfx950 70000000 16 1 2 4 3 0.1\ngfx950 70000000 16 1 2 4 8 0.1 extra\n"
+                 "otherarch 1 16 1 2 4 8 0.5\n")
     rc, applied, rejected = me.me_autotune_load(str(f))
-    assert rc == me.ME_OK and rejected == 3 and applied == 0
+    assert rc == me.ME_OK and rejected == 5 and applied == 0
     assert me.me_autotune_save(str(tmp_path / "out.txt")) == me.ME_OK
-    assert (tmp_path / "out.txt").read_text().startswith("# me autotune cache v1")
+    assert (tmp_path / "out.txt").read_text().startswith("# me autotune cache v2")
 
 
 def test_proposer_host_checks():

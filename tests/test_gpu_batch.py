@@ -94,7 +94,7 @@ def test_autotune_and_cache_roundtrip(streams, tmp_path):
     try:
         cfg, ms = me.autotune(pairs, 16, 15, reps=2)
         say("autotune best", cfg, ms)
-        assert cfg[0] in (1, 2, 4) and cfg[1] in (1, 2, 4, 8) and ms > 0
+        assert cfg[0] in (1, 2, 4) and cfg[1] in (1, 2, 4, 8) and cfg[2] in (1, 2, 4, 8, 16) and ms > 0
         assert me.me_get_config(16, 15) == cfg
         got = me.batch(pairs, 16, 15)
         for (cur, ref), g in zip(pairs, got):
@@ -112,6 +112,24 @@ def test_autotune_and_cache_roundtrip(streams, tmp_path):
         rows = [ln.split() for ln in path2.read_text().splitlines() if ln and not ln.startswith("#")]
         keys = [tuple(r[:4]) for r in rows]
         assert len(keys) == len(set(keys)), "a reloaded result is recorded twice"
+    finally:
+        me.set_config(16, 15, None)
+
+
+@pytest.mark.parametrize("grab", [1, 2, 8, 16])
+def test_tiles_per_grab(streams, grab):
+    """Every tiles-per-grab setting gives the single calls' results, in me_batch
+    and in me_batch_noalloc."""
+    pairs = pairs_of(streams, [3, 0, 2, 1, 5])
+    try:
+        rpl, wpg, _ = me.me_get_config(16, 15)
+        me.set_config(16, 15, (rpl, wpg, grab))
+        assert me.me_get_config(16, 15)[2] == grab
+        got = me.batch(pairs, 16, 15)
+        got2 = me.batch_noalloc(pairs, 16, 15)
+        for (cur, ref), g, g2 in zip(pairs, got, got2):
+            exp = me.dcds(cur, ref, 16, 15)
+            assert equal(g, exp) and equal(g2, exp), grab
     finally:
         me.set_config(16, 15, None)
 
