@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace me {
 namespace cnn {
 
@@ -64,6 +66,13 @@ struct SmallDiv {
 // max(x, 0) for finite x as one integer max on the bit pattern (negative
 // floats, -0 included, are negative integers); fmaxf would first quiet x.
 __device__ __forceinline__ float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
+// max(x, 0) of both bfloat16 halves of a packed pair, as signed 16-bit
+// integers (negative values, -0 included, have the sign bit set).
+typedef short v2s __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t relu_bf2(uint32_t x) {
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(v2s, x), (v2s){0, 0}));
+}
 
 // Two floats to a packed pair of bfloat16 (low = a), each rounded as f2bf.
 typedef float v2f __attribute__((ext_vector_type(2)));
@@ -490,52 +499,62 @@ __device__ __forceinline__ void conv_tile(const uint16_t* in, uint16_t* out, flo
         for (int r = 0; r < 4; ++r) bn[t][r] = t * 16 + 4 * kq + r < COUT ? bias[t * 16 + 4 * kq + r] : 0.f;
     const bool interior = oy0 >= 0 && ox0 >= 0 && oy0 + NO <= Ho && ox0 + NO <= Wo;
     const uint32_t ib = lds_addr(in), ob = HEAD ? lds_addr(head) : lds_addr(out);
-    for (int tile = wave; tile * 16 < M; tile += nw) {
-        // This lane's output pixel; past the layer it reads the last pixel
-        // and stores nothing.
-        const int po = tile * 16 + m;
-        const int pa = min(po, M - 1);
-        const int ay = SmallDiv<NO, M>::div(pa), ax = pa - __mul24(ay, NO);
-        const uint32_t ab = ib + 2u * (uint32_t)((S * ay * NI + S * ax) * PI) + (CIN >= 16 ? 8u * kq : 0u);
-        v4f acc[NT];
+    // The M-tile loop, with the test for outputs outside the layer's grid only
+    // where a tile reaches past it (BORDER; uniform per tile).
+    auto run = [&](auto border) {
+        constexpr bool BORDER = decltype(border)::value;
+        for (int tile = wave; tile * 16 < M; tile += nw) {
+            // This lane's output pixel; past the layer it reads the last pixel
+            // and stores nothing.
+            const int po = tile * 16 + m;
+            const int pa = min(po, M - 1);
+            const int ay = SmallDiv<NO, M>::div(pa), ax = pa - __mul24(ay, NO);
+            const uint32_t ab = ib + 2u * (uint32_t)((S * ay * NI + S * ax) * PI) + (CIN >= 16 ? 8u * kq : 0u);
+            v4f acc[NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t] = bn[t];
+            for (int t = 0; t < NT; ++t) acc[t] = bn[t];
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            uint32_t off;
-            if constexpr (CIN >= 16) {
-                const int tap = 16 * ks / CIN;
-                off = 2u * (uint32_t)(((tap / 3) * NI + tap % 3) * PI + 16 * ks % CIN);
-            } else {
-                off = aoff[ks];
+            for (int ks = 0; ks < KS; ++ks) {
+                uint32_t off;
+                if constexpr (CIN >= 16) {
+                    const int tap = 16 * ks / CIN;
+                    off = 2u * (uint32_t)(((tap / 3) * NI + tap % 3) * PI + 16 * ks % CIN);
+                } else {
+                    off = aoff[ks];
+                }
+                const v4s a = *lds_ptr<const v4s>(ab + off);
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(kCache ? w[kCache ? ks : 0][t] : weights(ks, t),
+                                                                      a, acc[t], 0, 0, 0);
             }
-            const v4s a = *lds_ptr<const v4s>(ab + off);
+            if (po >= M) continue;
+            // Outputs outside the layer's grid are the next layer's zero padding.
+            bool inside = true;
+            if constexpr (BORDER) inside = oy0 + ay >= 0 && oy0 + ay < Ho && ox0 + ax >= 0 && ox0 + ax < Wo;
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(kCache ? w[kCache ? ks : 0][t] : weights(ks, t), a,
-                                                                  acc[t], 0, 0, 0);
-        }
-        if (po >= M) continue;
-        // Outputs outside the layer's grid are the next layer's zero padding;
-        // a tile wholly inside (uniform) skips the test.
-        bool inside = true;
-        if (!HEAD && !interior) inside = oy0 + ay >= 0 && oy0 + ay < Ho && ox0 + ax >= 0 && ox0 + ax < Wo;
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const int n0 = t * 16 + 4 * kq;
-            if (n0 >= COUT) continue;
-            float v[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) v[r] = RELU ? relu(acc[t][r]) : acc[t][r];
-            if (HEAD) {
-                *lds_ptr<v4f>(ob + (uint32_t)__mul24(po, 16) + 4u * n0) = v4f{v[0], v[1], v[2], v[3]};
-            } else {
-                v2u o = v2u{pack_bf2(v[0], v[1]), pack_bf2(v[2], v[3])};
-                if (!inside) o = v2u{0u, 0u};
-                *lds_ptr<v2u>(ob + (uint32_t)__mul24(po, 2 * PO) + 2u * n0) = o;
+            for (int t = 0; t < NT; ++t) {
+                const int n0 = t * 16 + 4 * kq;
+                if (n0 >= COUT) continue;
+                if (HEAD) {
+                    *lds_ptr<v4f>(ob + (uint32_t)__mul24(po, 16) + 4u * n0) = acc[t];
+                } else {
+                    // ReLU on the packed bf16 pair: one signed 16-bit max each
+                    // (a negative value, -0 included, has its sign bit set), the
+                    // same values as ReLU before the rounding.
+                    v2u o = v2u{pack_bf2(acc[t][0], acc[t][1]), pack_bf2(acc[t][2], acc[t][3])};
+                    if (RELU) {
+                        o.x = relu_bf2(o.x);
+                        o.y = relu_bf2(o.y);
+                    }
+                    if (BORDER && !inside) o = v2u{0u, 0u};
+                    *lds_ptr<v2u>(ob + (uint32_t)__mul24(po, 2 * PO) + 2u * n0) = o;
+                }
             }
         }
-    }
+    };
+    if (HEAD || interior) run(std::false_type{});
+    else run(std::true_type{});
 }
 
 // The input tile (4x4 box means of cur and ref, as k_downdiff; 0 outside).
