@@ -3,10 +3,13 @@
 // This network is not part of the paper's method; its output only chooses
 // where DCDS starts.
 //
-// Tensors are NHWC bf16 (raw uint16).  Internally the first layer reads 4
-// input channels (the last two are zero) and the head writes 4 channels (the
-// last is zero), so that every 4 consecutive reduction indices (tap, channel)
-// of a convolution are one 8-byte load.
+// Tensors are NHWC bf16 (raw uint16).  The head writes 4 channels internally
+// (the last is zero).  Every 4 consecutive reduction indices of a convolution
+// are one 8-byte load: 4 channels of one tap for layers of 16 or more input
+// channels; for the 2-channel input of the first layer the taps of a kernel
+// row are paired by column (index (ky 4 + kx) 2 + ci, with a zero column
+// kx = 3 and a zero row ky = 3), so that the 4 indices are 2 adjacent pixels
+// and the reduction takes 2 k-steps of 16 instead of 3.
 //
 // Convolutions are implicit GEMMs on v_mfma_f32_16x16x16_bf16 (one wave per
 // 16x16 output tile).  Lane l holds A[l%16][4(l/16)+i] and B[4(l/16)+i][l%16],
@@ -28,13 +31,26 @@ struct LayerDim {
     int cin, cout, stride;
     bool relu;
 };
-// Internal layer shapes (first input and last output padded to 4 channels).
-constexpr LayerDim kLayers[4] = {{4, 16, 1, true}, {16, 32, 2, true}, {32, 32, 2, true}, {32, 4, 1, false}};
+// Internal layer shapes (last output padded to 4 channels).
+constexpr LayerDim kLayers[4] = {{2, 16, 1, true}, {16, 32, 2, true}, {32, 32, 2, true}, {32, 4, 1, false}};
 // Exposed (trained) shapes: 2 input channels, 3 head channels.
 constexpr int kExposedCin[4] = {2, 16, 32, 32};
 constexpr int kExposedCout[4] = {16, 32, 32, 3};
 
 __host__ __device__ constexpr int pad16(int v) { return (v + 15) / 16 * 16; }
+
+// Reduction index k of a layer with cin input channels: its tap and channel,
+// or tap = -1 for a padding index (zero weight).  cin = 2: the taps of a
+// kernel row paired by column, k = (ky 4 + kx) 2 + ci (32 indices, 18 used);
+// otherwise k = tap cin + ci.
+__host__ __device__ constexpr int ktap(int cin, int k) {
+    if (cin == 2) {
+        const int ky = k >> 3, kx = (k >> 1) & 3;
+        return ky < 3 && kx < 3 ? 3 * ky + kx : -1;
+    }
+    return k < 9 * cin ? k / cin : -1;
+}
+__host__ __device__ constexpr int kchan(int cin, int k) { return cin == 2 ? (k & 1) : k % cin; }
 
 // Round to bfloat16, nearest even (v_cvt_pk_bf16_f32).
 __device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
@@ -92,7 +108,7 @@ __device__ __forceinline__ __attribute__((address_space(3))) T* lds_ptr(uint32_t
 }
 
 // ---------------------------------------------------------------------------
-// Input: 4x4 box means of cur and ref -> [(c - r) / 32, (c - 128) / 64, 0, 0].
+// Input: 4x4 box means of cur and ref -> [(c - r) / 32, (c - 128) / 64].
 // One thread per output pixel; rows of 4 pixels are one aligned word.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_downdiff(const uint8_t* __restrict__ cur, const uint8_t* __restrict__ ref,
@@ -112,18 +128,15 @@ __global__ __launch_bounds__(256) void k_downdiff(const uint8_t* __restrict__ cu
     const float mc = (float)sc * (1.0f / 16.0f), mr = (float)sr * (1.0f / 16.0f);
     const uint16_t a = f2bf((mc - mr) * (1.0f / 32.0f));
     const uint16_t b = f2bf((mc - 128.0f) * (1.0f / 64.0f));
-    uint2 out;
-    out.x = (uint32_t)a | ((uint32_t)b << 16);
-    out.y = 0u;
-    *reinterpret_cast<uint2*>(x0 + (((long long)p * H4 + y) * W4 + x) * 4) = out;
+    *reinterpret_cast<uint32_t*>(x0 + (((long long)p * H4 + y) * W4 + x) * 2) = (uint32_t)a | ((uint32_t)b << 16);
 }
 
 // ---------------------------------------------------------------------------
 // Forward convolution: out[p][oy][ox][co] = bias[co] + sum_{tap, ci}
 //   in[p][oy*S + ky - 1][ox*S + kx - 1][ci] * W[tap][ci][co]    (tap = 3 ky + kx),
 // accumulated from the bias.
-// GEMM M = 16 output pixels of one row, N = COUT, K = 9 CIN (k = tap*CIN + ci).
-// Wf: [COUT][KP] bf16, KP = pad16(9 CIN), zero beyond 9 CIN.
+// GEMM M = 16 output pixels of one row, N = COUT, K = 9 CIN in the order of
+// ktap/kchan.  Wf: [COUT][KP] bf16, KP = pad16(9 CIN), zero at padding indices.
 // ---------------------------------------------------------------------------
 template <int CIN, int COUT, int S, bool RELU, bool F32OUT>
 __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ in, const uint16_t* __restrict__ Wf,
@@ -148,12 +161,23 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ i
 #pragma unroll 2
     for (int ks = 0; ks < KP / 16; ++ks) {
         const int k = ks * 16 + 4 * kq;
-        const int tap = k / CIN, ci = k % CIN;
         uint2 av = make_uint2(0u, 0u);
-        if (tap < 9 && ox < Wo) {
-            const int iy = oy * S + tap / 3 - 1, ix = ox * S + tap % 3 - 1;
-            if (iy >= 0 && iy < Hi && ix >= 0 && ix < Wi)
-                av = *reinterpret_cast<const uint2*>(inp + ((long long)iy * Wi + ix) * CIN + ci);
+        if constexpr (CIN == 2) {
+            // Two column-adjacent taps of one kernel row, both channels each.
+            const int ky = k >> 3, kx = (k >> 1) & 3;
+            const int iy = oy * S + ky - 1, ix = ox * S + kx - 1;
+            if (ky < 3 && ox < Wo && iy >= 0 && iy < Hi) {
+                const uint32_t* row = reinterpret_cast<const uint32_t*>(inp + (long long)iy * Wi * 2);
+                if (ix >= 0 && ix < Wi) av.x = row[ix];
+                if (kx + 1 < 3 && ix + 1 >= 0 && ix + 1 < Wi) av.y = row[ix + 1];
+            }
+        } else {
+            const int tap = k / CIN, ci = k % CIN;
+            if (tap < 9 && ox < Wo) {
+                const int iy = oy * S + tap / 3 - 1, ix = ox * S + tap % 3 - 1;
+                if (iy >= 0 && iy < Hi && ix >= 0 && ix < Wi)
+                    av = *reinterpret_cast<const uint2*>(inp + ((long long)iy * Wi + ix) * CIN + ci);
+            }
         }
         const v4s a = as_v4s(av);
 #pragma unroll
@@ -380,14 +404,16 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ w, const float
 }
 
 // bf16 operand layouts of one layer from its fp32 master W[tap][ci][co]:
-// forward Wf[co][tap*CIN + ci] and input-gradient Wb[ci][tap*COUT + co].
+// forward Wf[co][k] (k in the order of ktap/kchan) and input-gradient
+// Wb[ci][tap*COUT + co].
 __global__ __launch_bounds__(256) void k_pack_weights(const float* __restrict__ W, int cin, int cout,
                                                       uint16_t* __restrict__ wf, uint16_t* __restrict__ wb) {
     const int kp = pad16(9 * cin), kb = pad16(9 * cout);
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i < cout * kp) {
         const int co = i / kp, k = i % kp;
-        wf[i] = k < 9 * cin ? f2bf(W[(k / cin * cin + k % cin) * cout + co]) : (uint16_t)0;
+        const int tap = ktap(cin, k);
+        wf[i] = tap >= 0 ? f2bf(W[(tap * cin + kchan(cin, k)) * cout + co]) : (uint16_t)0;
     }
     if (wb && i < cin * kb) {
         const int ci = i / kb, k = i % kb;
@@ -433,7 +459,7 @@ __global__ __launch_bounds__(256) void k_head_export(const float* __restrict__ h
 // ---------------------------------------------------------------------------
 constexpr int kTB = 8;
 constexpr int kN3 = kTB + 2, kN2 = 2 * kN3 + 1, kN1 = 2 * kN2 + 1, kN0 = kN1 + 2;
-constexpr int kP0 = 4, kP1 = 20, kP2 = 44, kP3 = 40;  // pixel pitches
+constexpr int kP0 = 2, kP1 = 20, kP2 = 44, kP3 = 40;  // pixel pitches
 constexpr int kSz0 = kN0 * kN0 * kP0, kSz1 = kN1 * kN1 * kP1, kSz2 = kN2 * kN2 * kP2, kSz3 = kN3 * kN3 * kP3;
 // Weights in LDS: layer l as [COUT][KP + 4] bf16.
 __host__ __device__ constexpr int wrow(int l) { return pad16(9 * kLayers[l].cin) + 4; }
@@ -477,15 +503,19 @@ __device__ __forceinline__ void conv_tile(const uint16_t* in, uint16_t* out, flo
     };
     v4s w[kCache ? KS : 1][NT];
     // Operand byte offset of k-step ks: with CIN >= 16 a k-step stays within
-    // one tap, so it is a constant plus the lane's channel group.
+    // one tap, so it is a constant plus the lane's channel group; with CIN = 2
+    // the lane's 4 indices are the pixels (ky, kx) and (ky, kx + 1).
+    static_assert(CIN == 2 || CIN >= 16, "operand layouts of 2 or of 16+ channels");
     uint32_t aoff[CIN >= 16 ? 1 : KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-        if constexpr (CIN < 16) {
-            const int tap = (16 * ks + 4 * kq) / CIN, ci = (16 * ks + 4 * kq) % CIN;
-            // Padded reduction indices (tap >= 9) read the pixel itself:
-            // finite data against zero weights, which adds exact zeros.
-            aoff[ks] = 2u * (uint32_t)(tap < 9 ? ((tap / 3) * NI + tap % 3) * PI + ci : ci);
+        if constexpr (CIN == 2) {
+            const int ky = (16 * ks + 4 * kq) >> 3, kx = ((16 * ks + 4 * kq) >> 1) & 3;
+            // The padding row (ky = 3) reads the pixel itself, and the padding
+            // column (kx = 3) the pixel right of the window (one pixel past a
+            // tile row or, at the last one, past the tile, which is kept
+            // finite): finite data against zero weights adds exact zeros.
+            aoff[ks] = 2u * (uint32_t)(ky < 3 ? (ky * NI + kx) * PI : 0);
         }
         if constexpr (kCache)
 #pragma unroll
@@ -522,7 +552,17 @@ __device__ __forceinline__ void conv_tile(const uint16_t* in, uint16_t* out, flo
                 } else {
                     off = aoff[ks];
                 }
-                const v4s a = *lds_ptr<const v4s>(ab + off);
+                v4s a;
+                if constexpr (CIN == 2) {
+                    // Two 4-byte pixels, 4-byte aligned: two dword reads (one
+                    // ds_read2_b32); an 8-byte read off an 8-byte boundary is
+                    // much slower.
+                    const __attribute__((address_space(3))) uint32_t* q = lds_ptr<const uint32_t>(ab + off);
+                    const uint32_t lo = q[0], hi = q[1];
+                    a = __builtin_bit_cast(v4s, make_uint2(lo, hi));
+                } else {
+                    a = *lds_ptr<const v4s>(ab + off);
+                }
 #pragma unroll
                 for (int t = 0; t < NT; ++t)
                     acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(kCache ? w[kCache ? ks : 0][t] : weights(ks, t),
@@ -569,7 +609,7 @@ constexpr int kInG = (kN0 + 3) / 4;  // items per row; the last holds kN0 - 4 (k
 constexpr int kInItems = kN0 * kInG;
 
 __device__ __forceinline__ void input_item(int it, const uint8_t* cp, const uint8_t* rp, int pitch, int y0, int x0,
-                                           int H4, int W4, uint2 (&o)[4]) {
+                                           int H4, int W4, uint32_t (&o)[4]) {
     const int i = it / kInG, q = it - (it / kInG) * kInG;
     const int gy = y0 + i, gx = x0 + 4 * q;
     const bool in = gy >= 0 && gy < H4 && gx >= 0 && gx < W4;
@@ -597,25 +637,23 @@ __device__ __forceinline__ void input_item(int it, const uint8_t* cp, const uint
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const float mc = (float)sc[u] * (1.0f / 16.0f), mr = (float)sr[u] * (1.0f / 16.0f);
-        o[u] = in ? make_uint2((uint32_t)f2bf((mc - mr) * (1.0f / 32.0f)) |
-                                   ((uint32_t)f2bf((mc - 128.0f) * (1.0f / 64.0f)) << 16),
-                               0u)
-                  : make_uint2(0u, 0u);
+        o[u] = in ? (uint32_t)f2bf((mc - mr) * (1.0f / 32.0f)) | ((uint32_t)f2bf((mc - 128.0f) * (1.0f / 64.0f)) << 16)
+                  : 0u;
     }
 }
 
-__device__ __forceinline__ void input_store(uint16_t* x, int it, const uint2 (&o)[4]) {
+__device__ __forceinline__ void input_store(uint16_t* x, int it, const uint32_t (&o)[4]) {
     const int i = it / kInG, q = it - (it / kInG) * kInG;
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-        if (4 * q + u < kN0) *reinterpret_cast<uint2*>(x + (i * kN0 + 4 * q + u) * kP0) = o[u];
+        if (4 * q + u < kN0) *reinterpret_cast<uint32_t*>(x + (i * kN0 + 4 * q + u) * kP0) = o[u];
 }
 
 // Layer 3's M-tiles take waves [0, kW3); the rest load the next tile's input
 // meanwhile.
 constexpr int kW3 = (kN3 * kN3 + 15) / 16;
 static_assert((kFusedThreads / 64 - kW3) * 64 >= kInItems, "input prefetch needs one item per idle lane");
-static_assert(kSz0 <= kSz2, "the input tile lives in layer 2's buffer");
+static_assert(kSz0 + kP0 <= kSz2, "the input tile, and the pixel after it, live in layer 2's buffer");
 
 // grid: min(tiles, CUs) workgroups of kFusedThreads threads, kFusedLds bytes.
 // wf/bias: the packed layer weights ([COUT][KP]) and biases.
@@ -675,11 +713,14 @@ __global__ __launch_bounds__(kFusedThreads) void k_proposer_infer(
         bx0 = (r % tx) * kTB;
         by0 = (r / tx) * kTB;
     };
+    // The pixel after the input tile (read against zero weights) starts
+    // finite; later it holds layer-2 values, finite too.
+    if (threadIdx.x < kP0) l2[kSz0 + threadIdx.x] = 0;
     if (first < end) {
         int p, by0, bx0;
         place(first, p, by0, bx0);
         for (int it = threadIdx.x; it < kInItems; it += blockDim.x) {
-            uint2 o[4];
+            uint32_t o[4];
             input_item(it, cur + (long long)p * pair_stride, ref + (long long)p * pair_stride, pitch, 4 * by0 - 8,
                        4 * bx0 - 8, H4, W4, o);
             input_store(l2, it, o);
@@ -693,14 +734,14 @@ __global__ __launch_bounds__(kFusedThreads) void k_proposer_infer(
         const int y3 = by0 - 1, x3 = bx0 - 1;
         const int y2 = 2 * y3 - 1, x2 = 2 * x3 - 1;
         const int y1 = 2 * y2 - 1, x1 = 2 * x2 - 1;
-        conv_tile<4, 16, 1, kN0, kN1, kP0, kP1, true, false>(l2, l1, nullptr, wl, bl, y1, x1, H4, W4);
+        conv_tile<2, 16, 1, kN0, kN1, kP0, kP1, true, false>(l2, l1, nullptr, wl, bl, y1, x1, H4, W4);
         __syncthreads();
         conv_tile<16, 32, 2, kN1, kN2, kP1, kP2, true, false>(l1, l2, nullptr, wl + kWOff1, bl + 16, y2, x2, H8, W8);
         __syncthreads();
         conv_tile<32, 32, 2, kN2, kN3, kP2, kP3, true, false>(l2, l3, nullptr, wl + kWOff2, bl + 48, y3, x3, Hb, Wb);
         const int it = (int)threadIdx.x - 64 * kW3;
         const bool fetch = wave >= kW3 && t + step < end && it < kInItems;
-        uint2 o[4];
+        uint32_t o[4];
         if (fetch) {
             int pn, byn, bxn;
             place(t + step, pn, byn, bxn);

@@ -151,7 +151,7 @@ int forward(me_proposer* p, const uint8_t* cur, const uint8_t* ref, int32_t widt
     if ((long long)n_pairs * H4 * W4 > (long long)INT32_MAX) return ME_EUNSUPPORTED;
     const long long P = n_pairs;
     int rc = ME_OK;
-    if ((rc = grow(&p->x0, &p->cx0, (size_t)(P * H4 * W4 * 4))) ||
+    if ((rc = grow(&p->x0, &p->cx0, (size_t)(P * H4 * W4 * 2))) ||
         (rc = grow(&p->x1, &p->cx1, (size_t)(P * H4 * W4 * 16))) ||
         (rc = grow(&p->x2, &p->cx2, (size_t)(P * H8 * W8 * 32))) ||
         (rc = grow(&p->x3, &p->cx3, (size_t)(P * H16 * W16 * 32))) ||
@@ -163,7 +163,7 @@ int forward(me_proposer* p, const uint8_t* cur, const uint8_t* ref, int32_t widt
     const Offsets oi = internal_offsets();
     hipLaunchKernelGGL(k_downdiff, dim3(cdiv(W4, 256), H4, n_pairs), dim3(256), 0, st, cur, ref, pitch, pair_stride,
                        H4, W4, p->x0);
-    hipLaunchKernelGGL((k_conv_fwd<4, 16, 1, true, false>), dim3(cdiv(W4, 64), H4, n_pairs), dim3(256), 0, st, p->x0,
+    hipLaunchKernelGGL((k_conv_fwd<2, 16, 1, true, false>), dim3(cdiv(W4, 64), H4, n_pairs), dim3(256), 0, st, p->x0,
                        p->wf[0], p->w + oi.b[0], (void*)p->x1, H4, W4, H4, W4);
     hipLaunchKernelGGL((k_conv_fwd<16, 32, 2, true, false>), dim3(cdiv(W8, 64), H8, n_pairs), dim3(256), 0, st, p->x1,
                        p->wf[1], p->w + oi.b[1], (void*)p->x2, H4, W4, H8, W8);
@@ -209,7 +209,7 @@ int backward(me_proposer* p, hipStream_t st) {
     if ((rc = weight_grad<16, 32, 2>(p, 1, p->x1, p->g2, H4, W4, H8, W8, st))) return rc;
     hipLaunchKernelGGL((k_conv_bwd_data<16, 32, 2>), dim3(cdiv(W4, 64), H4, p->P), dim3(256), 0, st, p->g2, p->wb[1],
                        p->x1, p->g1, H4, W4, H8, W8);
-    if ((rc = weight_grad<4, 16, 1>(p, 0, p->x0, p->g1, H4, W4, H4, W4, st))) return rc;
+    if ((rc = weight_grad<2, 16, 1>(p, 0, p->x0, p->g1, H4, W4, H4, W4, st))) return rc;
     return launched();
 }
 
