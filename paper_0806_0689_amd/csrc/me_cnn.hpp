@@ -491,6 +491,9 @@ __device__ __forceinline__ void conv_tile(const uint16_t* in, uint16_t* out, flo
     // Weights stay in registers across a wave's M-tiles when it has more
     // than one; otherwise each k-step reads its own.
     constexpr bool kCache = M > 16 * (kFusedThreads / 64);
+    // k-steps whose operand reads are issued together (register budget:
+    // 2 VGPRs per A operand, 2 NT more per k-step without cached weights).
+    constexpr int CH = kCache ? (KS < 9 ? KS : 9) : (KS < 6 ? KS : 6);
     const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (wave * 16 >= M) return;  // no output tile for this wave: skip the weight reads
@@ -543,30 +546,50 @@ __device__ __forceinline__ void conv_tile(const uint16_t* in, uint16_t* out, flo
             v4f acc[NT];
 #pragma unroll
             for (int t = 0; t < NT; ++t) acc[t] = bn[t];
+            // The k-steps in chunks of CH: every operand read of a chunk is
+            // issued before its MFMA chain starts (a scheduling barrier keeps
+            // the reads from sinking to their uses), so the reads' latencies
+            // overlap instead of adding up.
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                uint32_t off;
-                if constexpr (CIN >= 16) {
-                    const int tap = 16 * ks / CIN;
-                    off = 2u * (uint32_t)(((tap / 3) * NI + tap % 3) * PI + 16 * ks % CIN);
-                } else {
-                    off = aoff[ks];
-                }
-                v4s a;
-                if constexpr (CIN == 2) {
-                    // Two 4-byte pixels, 4-byte aligned: two dword reads (one
-                    // ds_read2_b32); an 8-byte read off an 8-byte boundary is
-                    // much slower.
-                    const __attribute__((address_space(3))) uint32_t* q = lds_ptr<const uint32_t>(ab + off);
-                    const uint32_t lo = q[0], hi = q[1];
-                    a = __builtin_bit_cast(v4s, make_uint2(lo, hi));
-                } else {
-                    a = *lds_ptr<const v4s>(ab + off);
-                }
+            for (int k0 = 0; k0 < KS; k0 += CH) {
+                v4s a[CH];
+                v4s wk[kCache ? 1 : CH][NT];
 #pragma unroll
-                for (int t = 0; t < NT; ++t)
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(kCache ? w[kCache ? ks : 0][t] : weights(ks, t),
-                                                                      a, acc[t], 0, 0, 0);
+                for (int c = 0; c < CH; ++c) {
+                    const int ks = k0 + c;
+                    if (ks >= KS) break;
+                    uint32_t off;
+                    if constexpr (CIN >= 16) {
+                        const int tap = 16 * ks / CIN;
+                        off = 2u * (uint32_t)(((tap / 3) * NI + tap % 3) * PI + 16 * ks % CIN);
+                    } else {
+                        off = aoff[ks];
+                    }
+                    if constexpr (CIN == 2) {
+                        // Two 4-byte pixels, 4-byte aligned: two dword reads
+                        // (one ds_read2_b32); an 8-byte read off an 8-byte
+                        // boundary is much slower.
+                        const __attribute__((address_space(3))) uint32_t* q = lds_ptr<const uint32_t>(ab + off);
+                        const uint32_t lo = q[0], hi = q[1];
+                        a[c] = __builtin_bit_cast(v4s, make_uint2(lo, hi));
+                    } else {
+                        a[c] = *lds_ptr<const v4s>(ab + off);
+                    }
+                    if constexpr (!kCache)
+#pragma unroll
+                        for (int t = 0; t < NT; ++t) wk[c][t] = weights(ks, t);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    const int ks = k0 + c;
+                    if (ks >= KS) break;
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(kCache ? w[kCache ? ks : 0][t]
+                                                                                  : wk[kCache ? 0 : c][t],
+                                                                          a[c], acc[t], 0, 0, 0);
+                }
             }
             if (po >= M) continue;
             // Outputs outside the layer's grid are the next layer's zero padding.
