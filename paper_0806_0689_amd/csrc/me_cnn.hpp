@@ -4,16 +4,22 @@
 // where DCDS starts.
 //
 // Tensors are NHWC bf16 (raw uint16).  The head writes 4 channels internally
-// (the last is zero).  Every 4 consecutive reduction indices of a convolution
-// are one 8-byte load: 4 channels of one tap for layers of 16 or more input
+// (the last is zero).
+//
+// Forward convolutions (training and the fused inference kernel alike) are
+// implicit GEMMs on v_mfma_f32_16x16x32_bf16, one wave per 16x16 output tile:
+// lane l holds A[l%16][8(l/16)+i] and B[8(l/16)+i][l%16], i = 0..7, and
+// receives D[4(l/16)+i][l%16], i = 0..3.  A lane's 8 reduction indices are
+// one 16-byte operand: 8 channels of one tap for layers of 16 or more input
 // channels; for the 2-channel input of the first layer the taps of a kernel
 // row are paired by column (index (ky 4 + kx) 2 + ci, with a zero column
-// kx = 3 and a zero row ky = 3), so that the 4 indices are 2 adjacent pixels
-// and the reduction takes 2 k-steps of 16 instead of 3.
+// kx = 3 and a zero row ky = 3), so that the 8 indices are 4 adjacent pixels
+// of one row and the whole reduction is one k-step.  The reduction is padded
+// to a multiple of 32 with zero weights.
 //
-// Convolutions are implicit GEMMs on v_mfma_f32_16x16x16_bf16 (one wave per
-// 16x16 output tile).  Lane l holds A[l%16][4(l/16)+i] and B[4(l/16)+i][l%16],
-// and receives D[4(l/16)+i][l%16], i = 0..3.
+// The backward kernels use v_mfma_f32_16x16x16_bf16 (lane l holds
+// A[l%16][4(l/16)+i] and B[4(l/16)+i][l%16], i = 0..3), with reductions
+// padded to a multiple of 16.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -26,6 +32,7 @@ namespace cnn {
 
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 struct LayerDim {
     int cin, cout, stride;
@@ -38,6 +45,9 @@ constexpr int kExposedCin[4] = {2, 16, 32, 32};
 constexpr int kExposedCout[4] = {16, 32, 32, 3};
 
 __host__ __device__ constexpr int pad16(int v) { return (v + 15) / 16 * 16; }
+__host__ __device__ constexpr int pad32(int v) { return (v + 31) / 32 * 32; }
+// Reduction length of the forward weights Wf[co][k] of a layer.
+__host__ __device__ constexpr int fwd_kp(int cin) { return pad32(9 * cin); }
 
 // Reduction index k of a layer with cin input channels: its tap and channel,
 // or tap = -1 for a padding index (zero weight).  cin = 2: the taps of a
@@ -57,6 +67,7 @@ __device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(ui
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 __device__ __forceinline__ v4s as_v4s(uint2 v) { return __builtin_bit_cast(v4s, v); }
+__device__ __forceinline__ v8bf as_v8bf(uint4 v) { return __builtin_bit_cast(v8bf, v); }
 
 // n / D for 0 <= n < N by one 24-bit multiply and a shift, where the
 // compiler's division by a constant takes a 32-bit high multiply: the
@@ -93,6 +104,7 @@ __device__ __forceinline__ uint32_t relu_bf2(uint32_t x) {
 // Two floats to a packed pair of bfloat16 (low = a), each rounded as f2bf.
 typedef float v2f __attribute__((ext_vector_type(2)));
 typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t pack_bf2(float a, float b) {
     return __builtin_bit_cast(uint32_t, __builtin_convertvector((v2f){a, b}, v2bf));
@@ -136,14 +148,15 @@ __global__ __launch_bounds__(256) void k_downdiff(const uint8_t* __restrict__ cu
 //   in[p][oy*S + ky - 1][ox*S + kx - 1][ci] * W[tap][ci][co]    (tap = 3 ky + kx),
 // accumulated from the bias.
 // GEMM M = 16 output pixels of one row, N = COUT, K = 9 CIN in the order of
-// ktap/kchan.  Wf: [COUT][KP] bf16, KP = pad16(9 CIN), zero at padding indices.
+// ktap/kchan.  Wf: [COUT][KP] bf16, KP = fwd_kp(CIN), zero at padding indices.
 // ---------------------------------------------------------------------------
 template <int CIN, int COUT, int S, bool RELU, bool F32OUT>
 __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ in, const uint16_t* __restrict__ Wf,
                                                   const float* __restrict__ bias, void* __restrict__ out, int Hi,
                                                   int Wi, int Ho, int Wo) {
-    constexpr int KP = pad16(9 * CIN);
+    constexpr int KP = fwd_kp(CIN);
     constexpr int NT = (COUT + 15) / 16;
+    static_assert(CIN == 2 || CIN % 8 == 0, "8 reduction indices of a lane share one tap");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int seg = blockIdx.x * 4 + wave;
     const int oy = blockIdx.y, p = blockIdx.z;
@@ -158,36 +171,37 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ i
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[t][r] = t * 16 + 4 * kq + r < COUT ? bias[t * 16 + 4 * kq + r] : 0.f;
     const uint16_t* inp = in + (long long)p * Hi * Wi * CIN;
-#pragma unroll 2
-    for (int ks = 0; ks < KP / 16; ++ks) {
-        const int k = ks * 16 + 4 * kq;
-        uint2 av = make_uint2(0u, 0u);
+#pragma unroll 3
+    for (int ks = 0; ks < KP / 32; ++ks) {
+        const int k = ks * 32 + 8 * kq;
+        uint4 av = make_uint4(0u, 0u, 0u, 0u);
         if constexpr (CIN == 2) {
-            // Two column-adjacent taps of one kernel row, both channels each.
-            const int ky = k >> 3, kx = (k >> 1) & 3;
-            const int iy = oy * S + ky - 1, ix = ox * S + kx - 1;
+            // Kernel row ky = kq: the taps kx = 0..2, both channels each (kx = 3
+            // and ky = 3 are zero padding).
+            const int ky = k >> 3;
+            const int iy = oy * S + ky - 1, ix = ox * S - 1;
             if (ky < 3 && ox < Wo && iy >= 0 && iy < Hi) {
                 const uint32_t* row = reinterpret_cast<const uint32_t*>(inp + (long long)iy * Wi * 2);
-                if (ix >= 0 && ix < Wi) av.x = row[ix];
-                if (kx + 1 < 3 && ix + 1 >= 0 && ix + 1 < Wi) av.y = row[ix + 1];
+                if (ix >= 0) av.x = row[ix];
+                if (ix + 1 < Wi) av.y = row[ix + 1];
+                if (ix + 2 < Wi) av.z = row[ix + 2];
             }
         } else {
             const int tap = k / CIN, ci = k % CIN;
             if (tap < 9 && ox < Wo) {
                 const int iy = oy * S + tap / 3 - 1, ix = ox * S + tap % 3 - 1;
                 if (iy >= 0 && iy < Hi && ix >= 0 && ix < Wi)
-                    av = *reinterpret_cast<const uint2*>(inp + ((long long)iy * Wi + ix) * CIN + ci);
+                    av = *reinterpret_cast<const uint4*>(inp + ((long long)iy * Wi + ix) * CIN + ci);
             }
         }
-        const v4s a = as_v4s(av);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             const int n = t * 16 + m;
-            uint2 bv = make_uint2(0u, 0u);
-            if (n < COUT) bv = *reinterpret_cast<const uint2*>(Wf + (long long)n * KP + k);
+            uint4 bv = make_uint4(0u, 0u, 0u, 0u);
+            if (n < COUT) bv = *reinterpret_cast<const uint4*>(Wf + (long long)n * KP + k);
             // Weights as the row operand: lane (m, kq) receives channels
             // 16 t + 4 kq .. + 3 of pixel ox.
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(as_v4s(bv), a, acc[t], 0, 0, 0);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_v8bf(bv), as_v8bf(av), acc[t], 0, 0, 0);
         }
     }
     if (ox >= Wo) return;
@@ -408,7 +422,7 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ w, const float
 // Wb[ci][tap*COUT + co].
 __global__ __launch_bounds__(256) void k_pack_weights(const float* __restrict__ W, int cin, int cout,
                                                       uint16_t* __restrict__ wf, uint16_t* __restrict__ wb) {
-    const int kp = pad16(9 * cin), kb = pad16(9 * cout);
+    const int kp = fwd_kp(cin), kb = pad16(9 * cout);
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i < cout * kp) {
         const int co = i / kp, k = i % kp;
@@ -447,78 +461,107 @@ __global__ __launch_bounds__(256) void k_head_export(const float* __restrict__ h
 // Fused inference: all four layers for a tile of kTB x kTB blocks, with every
 // activation in LDS, then the start-vector decode.  Each output takes exactly
 // the operands and the k-step order of k_downdiff + k_conv_fwd + k_head_decode
-// (same bf16 values, same 16-wide MFMA steps in the same order, zero padding
+// (same bf16 values, same 32-wide MFMA k-steps in the same order, zero padding
 // outside each layer's image), so the two paths give identical results.
 //
 // Tile sides (with the halo each 3x3 layer needs): L3 kN3 = kTB + 2, L2
-// kN2 = 2 kN3 + 1, L1 kN1 = 2 kN2 + 1, input kN0 = kN1 + 2.  Per-pixel
-// pitches (in bf16) pad the NHWC rows so that the 16 pixels of an MFMA
-// operand fall into different LDS banks.  Persistent: one workgroup per CU
-// stages the weights once (rows padded by 4 for the same reason) and walks
-// the tiles.
+// kN2 = 2 kN3 + 1, L1 kN1 = 2 kN2 + 1, input kN0 = kN1 + 2.  Persistent: one
+// workgroup per CU stages the weights once and walks the tiles.
+//
+// LDS layouts are chosen so that the 16 lanes reading one operand row read
+// 16 consecutive 16-byte words (one ds_read_b128 each, free of bank
+// conflicts):
+// - activations (Planar): 8 channels of a pixel are one 16-byte slot; the
+//   channel groups are separate planes; and where the next layer reads with
+//   stride 2 each row keeps its even columns first, so that one tap of 16
+//   consecutive stride-2 outputs is 16 consecutive slots;
+// - weights: the 16-byte chunk (k-step, lane group, output channel), output
+//   channel fastest.
+// The 2-channel input tile is one dword per pixel.
 // ---------------------------------------------------------------------------
 constexpr int kTB = 8;
 constexpr int kN3 = kTB + 2, kN2 = 2 * kN3 + 1, kN1 = 2 * kN2 + 1, kN0 = kN1 + 2;
-constexpr int kP0 = 2, kP1 = 20, kP2 = 44, kP3 = 40;  // pixel pitches
-constexpr int kSz0 = kN0 * kN0 * kP0, kSz1 = kN1 * kN1 * kP1, kSz2 = kN2 * kN2 * kP2, kSz3 = kN3 * kN3 * kP3;
-// Weights in LDS: layer l as [COUT][KP + 4] bf16.
-__host__ __device__ constexpr int wrow(int l) { return pad16(9 * kLayers[l].cin) + 4; }
-__host__ __device__ constexpr int wsize(int l) { return kLayers[l].cout * wrow(l); }
-constexpr int kWOff1 = wsize(0), kWOff2 = kWOff1 + wsize(1), kWOff3 = kWOff2 + wsize(2), kWAll = kWOff3 + wsize(3);
+
+template <int N, int C, bool SPLIT>
+struct Planar {
+    static_assert(C % 8 == 0, "whole 16-byte slots");
+    static constexpr int kEven = (N + 1) / 2;                // even columns per row
+    static constexpr int kPlane = (N * N + 15) / 16 * 16;    // plane stride in slots (a 256-byte multiple)
+    static constexpr int kBytes = 16 * (C / 8) * kPlane;
+    __host__ __device__ static constexpr int col(int x) { return SPLIT ? ((x & 1) ? kEven + (x >> 1) : (x >> 1)) : x; }
+};
+typedef Planar<kN1, 16, true> L1Tile;   // L1 output, read by L2 (stride 2)
+typedef Planar<kN2, 32, true> L2Tile;   // L2 output, read by L3 (stride 2)
+typedef Planar<kN3, 32, false> L3Tile;  // L3 output, read by the head (stride 1)
+constexpr int kIn0Bytes = 4 * (kN0 * kN0 + 1);  // input tile and the pixel after it
+static_assert(kIn0Bytes <= L2Tile::kBytes, "the input tile lives in layer 2's buffer");
+
+// Weights in LDS: layer l as 16-byte chunks [KS][4][COUT].
+__host__ __device__ constexpr int wbytes(int l) { return fwd_kp(kLayers[l].cin) / 8 * 16 * kLayers[l].cout; }
+constexpr int kWOff1 = wbytes(0), kWOff2 = kWOff1 + wbytes(1), kWOff3 = kWOff2 + wbytes(2), kWAll = kWOff3 + wbytes(3);
 constexpr int kBias = 16 + 32 + 32 + 4;
-// LDS: l1, l2 (also the input tile), l3, the weights, then the fp32 head
-// (16-byte aligned for its 4-channel stores) and the biases.
-constexpr size_t kHeadByte = (2 * (size_t)(kSz1 + kSz2 + kSz3 + kWAll) + 15) / 16 * 16;
-constexpr size_t kFusedLds = kHeadByte + 4 * (size_t)(4 * kTB * kTB + kBias);
+// LDS (bytes): l1, l2 (also the input tile), l3, the weights, the fp32 head
+// and the biases.
+constexpr int kOffL2 = L1Tile::kBytes, kOffL3 = kOffL2 + L2Tile::kBytes, kOffW = kOffL3 + L3Tile::kBytes;
+constexpr int kOffHead = kOffW + kWAll, kOffBias = kOffHead + 4 * 4 * kTB * kTB;
+constexpr size_t kFusedLds = (size_t)kOffBias + 4 * kBias;
 constexpr int kFusedThreads = 1024;
+static_assert(kOffL2 % 16 == 0 && kOffL3 % 16 == 0 && kOffW % 16 == 0 && kOffHead % 16 == 0,
+              "16-byte aligned buffers");
+static_assert(kFusedLds <= 160 * 1024, "one workgroup's LDS");
 
 // One 3x3 layer from an LDS tile to an LDS tile (or, for the head, to the
-// head buffer).  NI/NO: input/output tile sides; PI/PO: pixel pitches; W:
-// this layer's weights in LDS ([COUT][KP + 4]); (oy0, ox0): output tile
-// origin in its layer's grid of Ho x Wo (outputs outside are written as 0,
-// the next layer's padding).  The weights are the MFMA row operand and 16
-// output pixels the column operand, so lane (m, kq) receives channels
-// 16 t + 4 kq .. + 3 of pixel m and stores them as one 8-byte word.  A lane's
-// operand address is a per-tile base plus a per-k-step offset fixed for the
-// layer.
-template <int CIN, int COUT, int S, int NI, int NO, int PI, int PO, bool RELU, bool HEAD>
-__device__ __forceinline__ void conv_tile(const uint16_t* in, uint16_t* out, float* head, const uint16_t* W,
-                                          const float* bias, int oy0, int ox0, int Ho, int Wo) {
-    constexpr int KP = pad16(9 * CIN);
-    constexpr int KS = KP / 16;
+// head buffer).  LI/LO: input/output layouts (LI unused for the 2-channel
+// input: one dword per pixel, side NI); NO: output tile side; W: this
+// layer's weight chunks; (oy0, ox0): output tile origin in its layer's grid of
+// Ho x Wo (outputs outside are written as 0, the next layer's padding).  The
+// weights are the MFMA row operand and 16 output pixels the column operand,
+// so lane (m, kq) receives channels 16 t + 4 kq .. + 3 of pixel m and stores
+// them as one 8-byte word.  A lane's operand address is a per-tile base plus
+// a per-k-step offset fixed for the lane.
+template <int CIN, int COUT, int S, int NI, class LI, int NO, class LO, bool RELU, bool HEAD>
+__device__ __forceinline__ void conv_tile(uint32_t ib, uint32_t ob, uint32_t wb, const float* bias, int oy0, int ox0,
+                                          int Ho, int Wo) {
+    constexpr int KP = fwd_kp(CIN);
+    constexpr int KS = KP / 32;
     constexpr int NT = (COUT + 15) / 16;
     constexpr int M = NO * NO;
     // Weights stay in registers across a wave's M-tiles when it has more
     // than one; otherwise each k-step reads its own.
     constexpr bool kCache = M > 16 * (kFusedThreads / 64);
     // k-steps whose operand reads are issued together (register budget:
-    // 2 VGPRs per A operand, 2 NT more per k-step without cached weights).
-    constexpr int CH = kCache ? (KS < 9 ? KS : 9) : (KS < 6 ? KS : 6);
+    // 4 VGPRs per B operand, 4 NT more per k-step without cached weights).
+    constexpr int CH = kCache ? KS : (KS < 5 ? KS : 5);
     const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (wave * 16 >= M) return;  // no output tile for this wave: skip the weight reads
     const int m = lane & 15, kq = lane >> 4;
     auto weights = [&](int ks, int t) {
         const int n = t * 16 + m;
-        uint2 bv = make_uint2(0u, 0u);
-        if (n < COUT) bv = *reinterpret_cast<const uint2*>(W + n * (KP + 4) + ks * 16 + 4 * kq);
-        return as_v4s(bv);
+        v4u bv = v4u{0u, 0u, 0u, 0u};
+        if (n < COUT) bv = *lds_ptr<const v4u>(wb + 16u * (uint32_t)((ks * 4 + kq) * COUT + n));
+        return __builtin_bit_cast(v8bf, bv);
     };
-    v4s w[kCache ? KS : 1][NT];
-    // Operand byte offset of k-step ks: with CIN >= 16 a k-step stays within
-    // one tap, so it is a constant plus the lane's channel group; with CIN = 2
-    // the lane's 4 indices are the pixels (ky, kx) and (ky, kx + 1).
-    static_assert(CIN == 2 || CIN >= 16, "operand layouts of 2 or of 16+ channels");
-    uint32_t aoff[CIN >= 16 ? 1 : KS];
+    v8bf w[kCache ? KS : 1][NT];
+    // Operand byte offset of k-step ks: the tap and channel group of the
+    // lane's 8 indices; with CIN = 2 the pixels (ky, 0..3) of kernel row
+    // ky = kq.  A padding index reads the pixel itself (ky = 3, or a padding
+    // tap), or the pixel right of the window (kx = 3: one pixel past a tile
+    // row or, at the last one, past the tile, which is kept finite): finite
+    // data against zero weights adds exact zeros.
+    static_assert(CIN == 2 || CIN % 8 == 0, "8 reduction indices of a lane share one tap");
+    static_assert(CIN == 2 || S == 1 || (S == 2 && LI::col(2) == 1), "stride-2 inputs split even and odd columns");
+    uint32_t aoff[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
         if constexpr (CIN == 2) {
-            const int ky = (16 * ks + 4 * kq) >> 3, kx = ((16 * ks + 4 * kq) >> 1) & 3;
-            // The padding row (ky = 3) reads the pixel itself, and the padding
-            // column (kx = 3) the pixel right of the window (one pixel past a
-            // tile row or, at the last one, past the tile, which is kept
-            // finite): finite data against zero weights adds exact zeros.
-            aoff[ks] = 2u * (uint32_t)(ky < 3 ? (ky * NI + kx) * PI : 0);
+            aoff[ks] = 4u * (uint32_t)(kq < 3 ? kq * NI : 0);
+        } else {
+            const int k = 32 * ks + 8 * kq, tap = k / CIN < 9 ? k / CIN : 0, plane = k % CIN / 8;
+            const int kx = tap % 3;
+            // Column of tap kx relative to the output's first one.
+            const int cx = S == 2 ? (kx == 0 ? 0 : kx == 1 ? LI::kEven : 1) : kx;
+            aoff[ks] = 16u * (uint32_t)(plane * LI::kPlane + (tap / 3) * NI + cx);
         }
         if constexpr (kCache)
 #pragma unroll
@@ -531,7 +574,6 @@ __device__ __forceinline__ void conv_tile(const uint16_t* in, uint16_t* out, flo
 #pragma unroll
         for (int r = 0; r < 4; ++r) bn[t][r] = t * 16 + 4 * kq + r < COUT ? bias[t * 16 + 4 * kq + r] : 0.f;
     const bool interior = oy0 >= 0 && ox0 >= 0 && oy0 + NO <= Ho && ox0 + NO <= Wo;
-    const uint32_t ib = lds_addr(in), ob = HEAD ? lds_addr(head) : lds_addr(out);
     // The M-tile loop, with the test for outputs outside the layer's grid only
     // where a tile reaches past it (BORDER; uniform per tile).
     auto run = [&](auto border) {
@@ -542,7 +584,9 @@ __device__ __forceinline__ void conv_tile(const uint16_t* in, uint16_t* out, flo
             const int po = tile * 16 + m;
             const int pa = min(po, M - 1);
             const int ay = SmallDiv<NO, M>::div(pa), ax = pa - __mul24(ay, NO);
-            const uint32_t ab = ib + 2u * (uint32_t)((S * ay * NI + S * ax) * PI) + (CIN >= 16 ? 8u * kq : 0u);
+            // The output's first input pixel: (S ay, S ax), its column
+            // ax in a split row (the even columns first).
+            const uint32_t ab = CIN == 2 ? ib + 4u * (uint32_t)(ay * NI + ax) : ib + 16u * (uint32_t)(S * ay * NI + ax);
             v4f acc[NT];
 #pragma unroll
             for (int t = 0; t < NT; ++t) acc[t] = bn[t];
@@ -552,28 +596,21 @@ __device__ __forceinline__ void conv_tile(const uint16_t* in, uint16_t* out, flo
             // overlap instead of adding up.
 #pragma unroll
             for (int k0 = 0; k0 < KS; k0 += CH) {
-                v4s a[CH];
-                v4s wk[kCache ? 1 : CH][NT];
+                v8bf a[CH];
+                v8bf wk[kCache ? 1 : CH][NT];
 #pragma unroll
                 for (int c = 0; c < CH; ++c) {
                     const int ks = k0 + c;
                     if (ks >= KS) break;
-                    uint32_t off;
-                    if constexpr (CIN >= 16) {
-                        const int tap = 16 * ks / CIN;
-                        off = 2u * (uint32_t)(((tap / 3) * NI + tap % 3) * PI + 16 * ks % CIN);
-                    } else {
-                        off = aoff[ks];
-                    }
+                    const uint32_t ad = ab + aoff[ks];
                     if constexpr (CIN == 2) {
-                        // Two 4-byte pixels, 4-byte aligned: two dword reads
-                        // (one ds_read2_b32); an 8-byte read off an 8-byte
-                        // boundary is much slower.
-                        const __attribute__((address_space(3))) uint32_t* q = lds_ptr<const uint32_t>(ab + off);
-                        const uint32_t lo = q[0], hi = q[1];
-                        a[c] = __builtin_bit_cast(v4s, make_uint2(lo, hi));
+                        // 4 pixels at a 4-byte boundary: dword reads (two
+                        // ds_read2_b32); wider reads off their alignment are
+                        // much slower.
+                        const __attribute__((address_space(3))) uint32_t* q = lds_ptr<const uint32_t>(ad);
+                        a[c] = __builtin_bit_cast(v8bf, v4u{q[0], q[1], q[2], q[3]});
                     } else {
-                        a[c] = *lds_ptr<const v4s>(ab + off);
+                        a[c] = __builtin_bit_cast(v8bf, *lds_ptr<const v4u>(ad));
                     }
                     if constexpr (!kCache)
 #pragma unroll
@@ -586,9 +623,9 @@ __device__ __forceinline__ void conv_tile(const uint16_t* in, uint16_t* out, flo
                     if (ks >= KS) break;
 #pragma unroll
                     for (int t = 0; t < NT; ++t)
-                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(kCache ? w[kCache ? ks : 0][t]
-                                                                                  : wk[kCache ? 0 : c][t],
-                                                                          a[c], acc[t], 0, 0, 0);
+                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kCache ? w[kCache ? ks : 0][t]
+                                                                                : wk[kCache ? 0 : c][t],
+                                                                        a[c], acc[t], 0, 0, 0);
                 }
             }
             if (po >= M) continue;
@@ -599,7 +636,7 @@ __device__ __forceinline__ void conv_tile(const uint16_t* in, uint16_t* out, flo
             for (int t = 0; t < NT; ++t) {
                 const int n0 = t * 16 + 4 * kq;
                 if (n0 >= COUT) continue;
-                if (HEAD) {
+                if constexpr (HEAD) {
                     *lds_ptr<v4f>(ob + (uint32_t)__mul24(po, 16) + 4u * n0) = acc[t];
                 } else {
                     // ReLU on the packed bf16 pair: one signed 16-bit max each
@@ -611,7 +648,9 @@ __device__ __forceinline__ void conv_tile(const uint16_t* in, uint16_t* out, flo
                         o.y = relu_bf2(o.y);
                     }
                     if (BORDER && !inside) o = v2u{0u, 0u};
-                    *lds_ptr<v2u>(ob + (uint32_t)__mul24(po, 2 * PO) + 2u * n0) = o;
+                    // Channels n0 .. n0 + 3: plane n0 / 8, half (kq & 1) of the slot.
+                    const int slot = (n0 >> 3) * LO::kPlane + ay * NO + LO::col(ax);
+                    *lds_ptr<v2u>(ob + 16u * (uint32_t)slot + 8u * (uint32_t)(kq & 1)) = o;
                 }
             }
         }
@@ -665,21 +704,20 @@ __device__ __forceinline__ void input_item(int it, const uint8_t* cp, const uint
     }
 }
 
-__device__ __forceinline__ void input_store(uint16_t* x, int it, const uint32_t (&o)[4]) {
+__device__ __forceinline__ void input_store(uint32_t* x, int it, const uint32_t (&o)[4]) {
     const int i = it / kInG, q = it - (it / kInG) * kInG;
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-        if (4 * q + u < kN0) *reinterpret_cast<uint32_t*>(x + (i * kN0 + 4 * q + u) * kP0) = o[u];
+        if (4 * q + u < kN0) x[i * kN0 + 4 * q + u] = o[u];
 }
 
 // Layer 3's M-tiles take waves [0, kW3); the rest load the next tile's input
 // meanwhile.
 constexpr int kW3 = (kN3 * kN3 + 15) / 16;
 static_assert((kFusedThreads / 64 - kW3) * 64 >= kInItems, "input prefetch needs one item per idle lane");
-static_assert(kSz0 + kP0 <= kSz2, "the input tile, and the pixel after it, live in layer 2's buffer");
 
 // grid: min(tiles, CUs) workgroups of kFusedThreads threads, kFusedLds bytes.
-// wf/bias: the packed layer weights ([COUT][KP]) and biases.
+// wf/bias: the packed layer weights ([COUT][KP], KP = fwd_kp(CIN)) and biases.
 //
 // Per tile: L1 (input -> l1), L2 (l1 -> l2), then L3 (l2 -> l3) while the
 // idle waves fetch and reduce the next tile's input, then the head (l3 ->
@@ -690,24 +728,24 @@ __global__ __launch_bounds__(kFusedThreads) void k_proposer_infer(
     const uint16_t* __restrict__ wf2, const uint16_t* __restrict__ wf3, const float* __restrict__ b0,
     const float* __restrict__ b1, const float* __restrict__ b2, const float* __restrict__ b3, int R,
     int16_t* __restrict__ start, uint8_t* __restrict__ orient) {
-    extern __shared__ uint16_t lds[];
-    uint16_t* l1 = lds;
-    uint16_t* l2 = l1 + kSz1;  // the input tile, then layer 2
-    uint16_t* l3 = l2 + kSz2;
-    uint16_t* wl = l3 + kSz3;
-    float* head = reinterpret_cast<float*>(reinterpret_cast<char*>(lds) + kHeadByte);
-    float* bl = head + 4 * kTB * kTB;
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    uint32_t* x0 = reinterpret_cast<uint32_t*>(lds + kOffL2);  // the input tile, in layer 2's buffer
+    uint16_t* wl = reinterpret_cast<uint16_t*>(lds + kOffW);
+    float* head = reinterpret_cast<float*>(lds + kOffHead);
+    float* bl = reinterpret_cast<float*>(lds + kOffBias);
+    const uint32_t a1 = lds_addr(lds), a2 = a1 + kOffL2, a3 = a1 + kOffL3, aw = a1 + kOffW, ah = a1 + kOffHead;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     // Weights and biases, once.
     {
         const uint16_t* src[4] = {wf0, wf1, wf2, wf3};
-        const int off[4] = {0, kWOff1, kWOff2, kWOff3};
+        const int off[4] = {0, kWOff1 / 2, kWOff2 / 2, kWOff3 / 2};
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
-            const int kp = pad16(9 * kLayers[l].cin), rows = kLayers[l].cout;
-            for (int i = threadIdx.x; i < rows * (kp + 4); i += blockDim.x) {
-                const int n = i / (kp + 4), k = i % (kp + 4);
-                wl[off[l] + i] = k < kp ? src[l][n * kp + k] : (uint16_t)0;
+            const int kp = fwd_kp(kLayers[l].cin), rows = kLayers[l].cout;
+            for (int i = threadIdx.x; i < rows * kp; i += blockDim.x) {
+                // W[n][k], k = 32 ks + 8 kq + j -> chunk (ks, kq, n), element j.
+                const int n = i / kp, k = i % kp;
+                wl[off[l] + ((k >> 3) * rows + n) * 8 + (k & 7)] = src[l][i];
             }
         }
         for (int i = threadIdx.x; i < kBias; i += blockDim.x)
@@ -738,7 +776,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_proposer_infer(
     };
     // The pixel after the input tile (read against zero weights) starts
     // finite; later it holds layer-2 values, finite too.
-    if (threadIdx.x < kP0) l2[kSz0 + threadIdx.x] = 0;
+    if (threadIdx.x == 0) x0[kN0 * kN0] = 0;
     if (first < end) {
         int p, by0, bx0;
         place(first, p, by0, bx0);
@@ -746,7 +784,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_proposer_infer(
             uint32_t o[4];
             input_item(it, cur + (long long)p * pair_stride, ref + (long long)p * pair_stride, pitch, 4 * by0 - 8,
                        4 * bx0 - 8, H4, W4, o);
-            input_store(l2, it, o);
+            input_store(x0, it, o);
         }
     }
     __syncthreads();
@@ -757,11 +795,11 @@ __global__ __launch_bounds__(kFusedThreads) void k_proposer_infer(
         const int y3 = by0 - 1, x3 = bx0 - 1;
         const int y2 = 2 * y3 - 1, x2 = 2 * x3 - 1;
         const int y1 = 2 * y2 - 1, x1 = 2 * x2 - 1;
-        conv_tile<2, 16, 1, kN0, kN1, kP0, kP1, true, false>(l2, l1, nullptr, wl, bl, y1, x1, H4, W4);
+        conv_tile<2, 16, 1, kN0, L1Tile, kN1, L1Tile, true, false>(a2, a1, aw, bl, y1, x1, H4, W4);
         __syncthreads();
-        conv_tile<16, 32, 2, kN1, kN2, kP1, kP2, true, false>(l1, l2, nullptr, wl + kWOff1, bl + 16, y2, x2, H8, W8);
+        conv_tile<16, 32, 2, kN1, L1Tile, kN2, L2Tile, true, false>(a1, a2, aw + kWOff1, bl + 16, y2, x2, H8, W8);
         __syncthreads();
-        conv_tile<32, 32, 2, kN2, kN3, kP2, kP3, true, false>(l2, l3, nullptr, wl + kWOff2, bl + 48, y3, x3, Hb, Wb);
+        conv_tile<32, 32, 2, kN2, L2Tile, kN3, L3Tile, true, false>(a2, a3, aw + kWOff2, bl + 48, y3, x3, Hb, Wb);
         const int it = (int)threadIdx.x - 64 * kW3;
         const bool fetch = wave >= kW3 && t + step < end && it < kInItems;
         uint32_t o[4];
@@ -773,8 +811,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_proposer_infer(
         }
         __syncthreads();
         // Head over the kTB x kTB blocks: local L3 (1 + i, 1 + j) is block (by0 + i, bx0 + j).
-        conv_tile<32, 4, 1, kN3, kTB, kP3, 4, false, true>(l3, nullptr, head, wl + kWOff3, bl + 80, by0, bx0, Hb, Wb);
-        if (fetch) input_store(l2, it, o);
+        conv_tile<32, 4, 1, kN3, L3Tile, kTB, L3Tile, false, true>(a3, ah, aw + kWOff3, bl + 80, by0, bx0, Hb, Wb);
+        if (fetch) input_store(x0, it, o);
         __syncthreads();
         if (threadIdx.x < kTB * kTB) {
             const int i = threadIdx.x / kTB, j = threadIdx.x % kTB;

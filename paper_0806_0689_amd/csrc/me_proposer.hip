@@ -125,7 +125,7 @@ int pack_all(me_proposer* p, hipStream_t st) {
     const Offsets oi = internal_offsets();
     for (int l = 0; l < 4; ++l) {
         const int ci = kLayers[l].cin, co = kLayers[l].cout;
-        const int n = std::max(co * pad16(9 * ci), ci * pad16(9 * co));
+        const int n = std::max(co * fwd_kp(ci), ci * pad16(9 * co));
         hipLaunchKernelGGL(k_pack_weights, dim3(cdiv(n, 256)), dim3(256), 0, st, p->w + oi.w[l], ci, co, p->wf[l],
                            l > 0 ? p->wb[l] : nullptr);
     }
@@ -241,7 +241,7 @@ ME_EXPORT int me_proposer_create(me_proposer** out) {
               hipMalloc(&p->v, sizeof(float) * p->n_int) == hipSuccess;
     for (int l = 0; l < 4 && ok; ++l) {
         const int ci = kLayers[l].cin, co = kLayers[l].cout;
-        ok = hipMalloc(&p->wf[l], sizeof(uint16_t) * co * pad16(9 * ci)) == hipSuccess;
+        ok = hipMalloc(&p->wf[l], sizeof(uint16_t) * co * fwd_kp(ci)) == hipSuccess;
         if (ok && l > 0) ok = hipMalloc(&p->wb[l], sizeof(uint16_t) * ci * pad16(9 * co)) == hipSuccess;
     }
     if (ok) ok = hipMemset(p->w, 0, sizeof(float) * p->n_int) == hipSuccess &&
