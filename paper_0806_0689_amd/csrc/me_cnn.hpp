@@ -489,10 +489,13 @@ struct Planar {
     static constexpr int kPlane = (N * N + 15) / 16 * 16;    // plane stride in slots (a 256-byte multiple)
     static constexpr int kBytes = 16 * (C / 8) * kPlane;
     __host__ __device__ static constexpr int col(int x) { return SPLIT ? ((x & 1) ? kEven + (x >> 1) : (x >> 1)) : x; }
+    // The column stored at position c of a row (the inverse of col).
+    __host__ __device__ static constexpr int xof(int c) { return SPLIT ? 2 * c - (c < kEven ? 0 : 2 * kEven - 1) : c; }
 };
 typedef Planar<kN1, 16, true> L1Tile;   // L1 output, read by L2 (stride 2)
 typedef Planar<kN2, 32, true> L2Tile;   // L2 output, read by L3 (stride 2)
 typedef Planar<kN3, 32, false> L3Tile;  // L3 output, read by the head (stride 1)
+typedef Planar<kTB, 8, false> HeadTile;  // head output: 4 fp32 channels per pixel
 constexpr int kIn0Bytes = 4 * (kN0 * kN0 + 1);  // input tile and the pixel after it
 static_assert(kIn0Bytes <= L2Tile::kBytes, "the input tile lives in layer 2's buffer");
 
@@ -511,30 +514,44 @@ static_assert(kOffL2 % 16 == 0 && kOffL3 % 16 == 0 && kOffW % 16 == 0 && kOffHea
 static_assert(kFusedLds <= 160 * 1024, "one workgroup's LDS");
 
 // One 3x3 layer from an LDS tile to an LDS tile (or, for the head, to the
-// head buffer).  LI/LO: input/output layouts (LI unused for the 2-channel
-// input: one dword per pixel, side NI); NO: output tile side; W: this
-// layer's weight chunks; (oy0, ox0): output tile origin in its layer's grid of
-// Ho x Wo (outputs outside are written as 0, the next layer's padding).  The
-// weights are the MFMA row operand and 16 output pixels the column operand,
-// so lane (m, kq) receives channels 16 t + 4 kq .. + 3 of pixel m and stores
-// them as one 8-byte word.  A lane's operand address is a per-tile base plus
-// a per-k-step offset fixed for the lane.
-template <int CIN, int COUT, int S, int NI, class LI, int NO, class LO, bool RELU, bool HEAD>
+// head buffer: fp32, 4 channels, 16 bytes per pixel).  LI/LO: input/output
+// layouts (LI unused for the 2-channel input: one dword per pixel, side NI);
+// NO: output tile side; wb: this layer's weight chunks; (oy0, ox0): output
+// tile origin in its layer's grid of Ho x Wo (outputs outside are written as
+// 0, the next layer's padding).  The weights are the MFMA row operand and 16
+// output pixels the column operand, so lane (m, kq) receives channels
+// 16 t + 4 kq .. + 3 of pixel m and stores them as one 8-byte word.
+//
+// Output pixels are numbered in the output layout's stored order (so a
+// lane's store address is its index times 16 plus a lane constant) and cut
+// into PARTS bands of HR rows: an M-tile of the first band and the M-tiles
+// HR rows below it in the other bands are computed together, at constant
+// offsets from the first one's addresses.  Rows past the layer (in the last
+// band) read inside LDS and are not stored.
+template <int CIN, int COUT, int S, int NI, class LI, int NO, class LO, int PARTS, bool RELU, bool HEAD>
 __device__ __forceinline__ void conv_tile(uint32_t ib, uint32_t ob, uint32_t wb, const float* bias, int oy0, int ox0,
                                           int Ho, int Wo) {
     constexpr int KP = fwd_kp(CIN);
     constexpr int KS = KP / 32;
     constexpr int NT = (COUT + 15) / 16;
     constexpr int M = NO * NO;
+    constexpr int HR = (NO + PARTS - 1) / PARTS, MB = HR * NO;
     // Weights stay in registers across a wave's M-tiles when it has more
     // than one; otherwise each k-step reads its own.
-    constexpr bool kCache = M > 16 * (kFusedThreads / 64);
+    constexpr bool kCache = MB > 16 * (kFusedThreads / 64);
     // k-steps whose operand reads are issued together (register budget:
-    // 4 VGPRs per B operand, 4 NT more per k-step without cached weights).
-    constexpr int CH = kCache ? KS : (KS < 5 ? KS : 5);
+    // 4 VGPRs per B operand and band, 4 NT more per k-step without cached
+    // weights).
+    constexpr int CMAX = kCache ? (PARTS == 1 ? 9 : 4) : (PARTS == 1 ? 5 : 3);
+    constexpr int CH = KS < CMAX ? KS : CMAX;
+    constexpr uint32_t kPix = CIN == 2 ? 4u : 16u;  // input bytes per pixel (per plane)
+    constexpr uint32_t kInBand = kPix * (uint32_t)(S * HR * NI), kOutBand = 16u * (uint32_t)MB;
+    static_assert(CIN == 2 || CIN % 8 == 0, "8 reduction indices of a lane share one tap");
+    static_assert(CIN == 2 || S == 1 || (S == 2 && LI::col(2) == 1), "stride-2 inputs split even and odd columns");
+    static_assert(!HEAD || (COUT == 4 && LO::kPlane >= M), "head: one 16-byte fp32 word per pixel");
     const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (wave * 16 >= M) return;  // no output tile for this wave: skip the weight reads
+    if (wave * 16 >= MB) return;  // no output tile for this wave: skip the weight reads
     const int m = lane & 15, kq = lane >> 4;
     auto weights = [&](int ks, int t) {
         const int n = t * 16 + m;
@@ -549,8 +566,6 @@ __device__ __forceinline__ void conv_tile(uint32_t ib, uint32_t ob, uint32_t wb,
     // tap), or the pixel right of the window (kx = 3: one pixel past a tile
     // row or, at the last one, past the tile, which is kept finite): finite
     // data against zero weights adds exact zeros.
-    static_assert(CIN == 2 || CIN % 8 == 0, "8 reduction indices of a lane share one tap");
-    static_assert(CIN == 2 || S == 1 || (S == 2 && LI::col(2) == 1), "stride-2 inputs split even and odd columns");
     uint32_t aoff[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
@@ -573,44 +588,54 @@ __device__ __forceinline__ void conv_tile(uint32_t ib, uint32_t ob, uint32_t wb,
     for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int r = 0; r < 4; ++r) bn[t][r] = t * 16 + 4 * kq + r < COUT ? bias[t * 16 + 4 * kq + r] : 0.f;
+    // Store address of the lane's channels 4 kq .. + 3 (t = 0) for stored
+    // index 0: plane kq / 2, half kq & 1 of the slot.
+    const uint32_t obl = HEAD ? ob : ob + 16u * (uint32_t)((kq >> 1) * LO::kPlane) + 8u * (uint32_t)(kq & 1);
     const bool interior = oy0 >= 0 && ox0 >= 0 && oy0 + NO <= Ho && ox0 + NO <= Wo;
     // The M-tile loop, with the test for outputs outside the layer's grid only
     // where a tile reaches past it (BORDER; uniform per tile).
     auto run = [&](auto border) {
         constexpr bool BORDER = decltype(border)::value;
-        for (int tile = wave; tile * 16 < M; tile += nw) {
-            // This lane's output pixel; past the layer it reads the last pixel
-            // and stores nothing.
+        for (int tile = wave; tile * 16 < MB; tile += nw) {
+            // This lane's output pixel in band 0 (stored index po: row ay,
+            // stored column sc, column ax); past the band it takes the last
+            // pixel and stores nothing.
             const int po = tile * 16 + m;
-            const int pa = min(po, M - 1);
-            const int ay = SmallDiv<NO, M>::div(pa), ax = pa - __mul24(ay, NO);
-            // The output's first input pixel: (S ay, S ax), its column
-            // ax in a split row (the even columns first).
-            const uint32_t ab = CIN == 2 ? ib + 4u * (uint32_t)(ay * NI + ax) : ib + 16u * (uint32_t)(S * ay * NI + ax);
-            v4f acc[NT];
+            const int pa = min(po, MB - 1);
+            const int ay = SmallDiv<NO, MB>::div(pa), sc = pa - __mul24(ay, NO);
+            const int ax = LO::xof(sc);
+            // The output's first input pixel: (S ay, S ax), at column ax of a
+            // split row (even columns first) when S = 2.
+            const uint32_t ab = ib + kPix * (uint32_t)(S * ay * NI + ax);
+            v4f acc[PARTS][NT];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) acc[t] = bn[t];
+            for (int r = 0; r < PARTS; ++r)
+#pragma unroll
+                for (int t = 0; t < NT; ++t) acc[r][t] = bn[t];
             // The k-steps in chunks of CH: every operand read of a chunk is
             // issued before its MFMA chain starts (a scheduling barrier keeps
             // the reads from sinking to their uses), so the reads' latencies
             // overlap instead of adding up.
 #pragma unroll
             for (int k0 = 0; k0 < KS; k0 += CH) {
-                v8bf a[CH];
+                v8bf a[PARTS][CH];
                 v8bf wk[kCache ? 1 : CH][NT];
 #pragma unroll
                 for (int c = 0; c < CH; ++c) {
                     const int ks = k0 + c;
                     if (ks >= KS) break;
-                    const uint32_t ad = ab + aoff[ks];
-                    if constexpr (CIN == 2) {
-                        // 4 pixels at a 4-byte boundary: dword reads (two
-                        // ds_read2_b32); wider reads off their alignment are
-                        // much slower.
-                        const __attribute__((address_space(3))) uint32_t* q = lds_ptr<const uint32_t>(ad);
-                        a[c] = __builtin_bit_cast(v8bf, v4u{q[0], q[1], q[2], q[3]});
-                    } else {
-                        a[c] = __builtin_bit_cast(v8bf, *lds_ptr<const v4u>(ad));
+#pragma unroll
+                    for (int r = 0; r < PARTS; ++r) {
+                        const uint32_t ad = ab + aoff[ks] + (uint32_t)r * kInBand;
+                        if constexpr (CIN == 2) {
+                            // 4 pixels at a 4-byte boundary: dword reads (two
+                            // ds_read2_b32); wider reads off their alignment
+                            // are much slower.
+                            const __attribute__((address_space(3))) uint32_t* q = lds_ptr<const uint32_t>(ad);
+                            a[r][c] = __builtin_bit_cast(v8bf, v4u{q[0], q[1], q[2], q[3]});
+                        } else {
+                            a[r][c] = __builtin_bit_cast(v8bf, *lds_ptr<const v4u>(ad));
+                        }
                     }
                     if constexpr (!kCache)
 #pragma unroll
@@ -622,35 +647,40 @@ __device__ __forceinline__ void conv_tile(uint32_t ib, uint32_t ob, uint32_t wb,
                     const int ks = k0 + c;
                     if (ks >= KS) break;
 #pragma unroll
-                    for (int t = 0; t < NT; ++t)
-                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kCache ? w[kCache ? ks : 0][t]
-                                                                                : wk[kCache ? 0 : c][t],
-                                                                        a[c], acc[t], 0, 0, 0);
+                    for (int r = 0; r < PARTS; ++r)
+#pragma unroll
+                        for (int t = 0; t < NT; ++t)
+                            acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                kCache ? w[kCache ? ks : 0][t] : wk[kCache ? 0 : c][t], a[r][c], acc[r][t], 0, 0, 0);
                 }
             }
-            if (po >= M) continue;
-            // Outputs outside the layer's grid are the next layer's zero padding.
-            bool inside = true;
-            if constexpr (BORDER) inside = oy0 + ay >= 0 && oy0 + ay < Ho && ox0 + ax >= 0 && ox0 + ax < Wo;
+            if (po >= MB) continue;
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const int n0 = t * 16 + 4 * kq;
-                if (n0 >= COUT) continue;
-                if constexpr (HEAD) {
-                    *lds_ptr<v4f>(ob + (uint32_t)__mul24(po, 16) + 4u * n0) = acc[t];
-                } else {
-                    // ReLU on the packed bf16 pair: one signed 16-bit max each
-                    // (a negative value, -0 included, has its sign bit set), the
-                    // same values as ReLU before the rounding.
-                    v2u o = v2u{pack_bf2(acc[t][0], acc[t][1]), pack_bf2(acc[t][2], acc[t][3])};
-                    if (RELU) {
-                        o.x = relu_bf2(o.x);
-                        o.y = relu_bf2(o.y);
+            for (int r = 0; r < PARTS; ++r) {
+                if (r > 0 && po + r * MB >= M) break;
+                // Outputs outside the layer's grid are the next layer's zero padding.
+                bool inside = true;
+                if constexpr (BORDER)
+                    inside = oy0 + ay + r * HR >= 0 && oy0 + ay + r * HR < Ho && ox0 + ax >= 0 && ox0 + ax < Wo;
+                const uint32_t od = obl + 16u * (uint32_t)po + (uint32_t)r * kOutBand;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    if (16 * t + 4 * kq >= COUT) continue;
+                    if constexpr (HEAD) {
+                        *lds_ptr<v4f>(od) = acc[r][t];
+                    } else {
+                        // ReLU on the packed bf16 pair: one signed 16-bit max
+                        // each (a negative value, -0 included, has its sign bit
+                        // set), the same values as ReLU before the rounding.
+                        v2u o = v2u{pack_bf2(acc[r][t][0], acc[r][t][1]), pack_bf2(acc[r][t][2], acc[r][t][3])};
+                        if (RELU) {
+                            o.x = relu_bf2(o.x);
+                            o.y = relu_bf2(o.y);
+                        }
+                        if (BORDER && !inside) o = v2u{0u, 0u};
+                        // Channels 16 t + 4 kq .. + 3: plane 2 t + kq / 2.
+                        *lds_ptr<v2u>(od + 32u * (uint32_t)(t * LO::kPlane)) = o;
                     }
-                    if (BORDER && !inside) o = v2u{0u, 0u};
-                    // Channels n0 .. n0 + 3: plane n0 / 8, half (kq & 1) of the slot.
-                    const int slot = (n0 >> 3) * LO::kPlane + ay * NO + LO::col(ax);
-                    *lds_ptr<v2u>(ob + 16u * (uint32_t)slot + 8u * (uint32_t)(kq & 1)) = o;
                 }
             }
         }
@@ -795,11 +825,11 @@ __global__ __launch_bounds__(kFusedThreads) void k_proposer_infer(
         const int y3 = by0 - 1, x3 = bx0 - 1;
         const int y2 = 2 * y3 - 1, x2 = 2 * x3 - 1;
         const int y1 = 2 * y2 - 1, x1 = 2 * x2 - 1;
-        conv_tile<2, 16, 1, kN0, L1Tile, kN1, L1Tile, true, false>(a2, a1, aw, bl, y1, x1, H4, W4);
+        conv_tile<2, 16, 1, kN0, L1Tile, kN1, L1Tile, 2, true, false>(a2, a1, aw, bl, y1, x1, H4, W4);
         __syncthreads();
-        conv_tile<16, 32, 2, kN1, L1Tile, kN2, L2Tile, true, false>(a1, a2, aw + kWOff1, bl + 16, y2, x2, H8, W8);
+        conv_tile<16, 32, 2, kN1, L1Tile, kN2, L2Tile, 1, true, false>(a1, a2, aw + kWOff1, bl + 16, y2, x2, H8, W8);
         __syncthreads();
-        conv_tile<32, 32, 2, kN2, L2Tile, kN3, L3Tile, true, false>(a2, a3, aw + kWOff2, bl + 48, y3, x3, Hb, Wb);
+        conv_tile<32, 32, 2, kN2, L2Tile, kN3, L3Tile, 1, true, false>(a2, a3, aw + kWOff2, bl + 48, y3, x3, Hb, Wb);
         const int it = (int)threadIdx.x - 64 * kW3;
         const bool fetch = wave >= kW3 && t + step < end && it < kInItems;
         uint32_t o[4];
@@ -811,7 +841,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_proposer_infer(
         }
         __syncthreads();
         // Head over the kTB x kTB blocks: local L3 (1 + i, 1 + j) is block (by0 + i, bx0 + j).
-        conv_tile<32, 4, 1, kN3, L3Tile, kTB, L3Tile, false, true>(a3, ah, aw + kWOff3, bl + 80, by0, bx0, Hb, Wb);
+        conv_tile<32, 4, 1, kN3, L3Tile, kTB, HeadTile, 1, false, true>(a3, ah, aw + kWOff3, bl + 80, by0, bx0, Hb, Wb);
         if (fetch) input_store(x0, it, o);
         __syncthreads();
         if (threadIdx.x < kTB * kTB) {
