@@ -124,9 +124,10 @@ int me_dcds(const uint8_t *cur, const uint8_t *ref, int32_t width, int32_t heigh
  * DCDS with options.  algo: ME_ALGO_DCDS or ME_ALGO_DCDS_S.
  * start (optional, device, one per block): a proposed start vector, clamped
  * into the block's candidate set.  Plain DCDS runs first, from the origin;
- * then the start is evaluated, and only if its SAD is below the plain result's
- * does DCDS run again with its first cross centred on the start (the plain
- * result is the fallback, so the result is never worse than plain DCDS).
+ * then the start is evaluated, and only if its SAD is below the origin's does
+ * DCDS run again, with its first cross centred on the start, over the same
+ * evaluated point set.  The better of the two results is returned (a tie
+ * keeps the plain one), so the result is never worse than plain DCDS.
  * orient (optional, device, one byte per block): 0 = horizontal cross (the
  * paper's), 1 = vertical cross for that second search's first pattern.  nsp
  * counts every distinct point of both searches and the probe.  The learned
