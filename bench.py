@@ -413,9 +413,12 @@ def e2e_leg(me, torch, seq_np, dev, args):
 
 
 def small_config_leg(me, torch, dev, k, args):
-    """Configs 1 (176x144, one pair) and 2 (352x288, 300 frames, 299 pairs), 16x16
-    blocks, +-7: FS, plain DCDS and learned-start DCDS, one launch per step
-    over every pair of the sequence."""
+    """Configs 1 (176x144, one pair), 2 (352x288, 300 frames, 299 pairs) and 6
+    (352x288, 60 frames, the paper's operating point), 16x16 blocks, +-7: FS,
+    plain DCDS and learned-start DCDS, one launch per step over every pair of
+    the sequence.  Beside the §IV measures it reports how often DCDS finds the
+    FS vector (Table IX's probability, with FS as the truth) and how often FS
+    finds (0, 0) (Table II's centre probability)."""
     from synth import make_config
     seq_np = make_config(k)
     seq = torch.from_numpy(seq_np).to(dev)
@@ -426,17 +429,22 @@ def small_config_leg(me, torch, dev, k, args):
     blocks = P * (Hc // 16) * (Wc // 16)
     out = {"workload": "%dx%d uint8, %d frames (%d pairs), 16x16, +-%d, %d blocks per step" % (
         Wc, Hc, P + 1, P, R, blocks)}
+    mvs = {}
     for name, fn in (("fs", lambda: me.fullsearch(cur, ref, 16, R)), ("dcds", lambda: me.dcds(cur, ref, 16, R))):
-        _, sad, nsp = fn()
+        mvs[name], sad, nsp = fn()
         _, ms, _ = time_launches(fn, steps, args.warmup, torch)
         out[name] = {"mb_per_s": blocks / (ms * 1e-3), "ms_per_step": ms, "sad_mean": float(sad.double().mean()),
                      "nsp_mean": float(nsp.double().mean())}
     out["dcds"]["sad_over_fs"] = out["dcds"]["sad_mean"] / out["fs"]["sad_mean"]
+    out["dcds"]["p_fs_vector"] = float((mvs["dcds"] == mvs["fs"]).all(-1).double().mean())
+    out["fs"]["p_zero_vector"] = float((mvs["fs"] == 0).all(-1).double().mean())
     out["dcds_learned"] = learned_leg(me, torch, cur, ref, R, steps, args.warmup, out["fs"]["sad_mean"],
                                       out["dcds"])
-    print("# config%d: fs %.4f ms (%.3g MB/s), dcds %.4f ms (%.3g MB/s), sad/fs %.4f, nsp %.3f" % (
-        k, out["fs"]["ms_per_step"], out["fs"]["mb_per_s"], out["dcds"]["ms_per_step"], out["dcds"]["mb_per_s"],
-        out["dcds"]["sad_over_fs"], out["dcds"]["nsp_mean"]), file=sys.stderr, flush=True)
+    print("# config%d: fs %.4f ms (%.3g MB/s), dcds %.4f ms (%.3g MB/s), sad/fs %.4f, nsp %.3f, "
+          "P(dcds = fs) %.3f, P(fs = 0) %.3f" % (
+              k, out["fs"]["ms_per_step"], out["fs"]["mb_per_s"], out["dcds"]["ms_per_step"], out["dcds"]["mb_per_s"],
+              out["dcds"]["sad_over_fs"], out["dcds"]["nsp_mean"], out["dcds"]["p_fs_vector"],
+              out["fs"]["p_zero_vector"]), file=sys.stderr, flush=True)
     return out
 
 
@@ -476,7 +484,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only", default="",
                     help="comma list of extra legs to run (fs,dcds8,fs8,dcds_s,learned,batch,quality,mvp,e2e,"
-                         "config1,config2,4k); "
+                         "config1,config2,config6,4k); "
                          "dcds always runs")
     ap.add_argument("--sweep", action="store_true",
                     help="time every DCDS kernel configuration (rows per lane x waves per group) and exit")
@@ -509,7 +517,8 @@ def main():
     cur, ref = seq[1:], seq[:-1]
     P = FRAMES - 1
     legs = set(args.only.split(",")) if args.only else {"dcds", "fs", "dcds8", "fs8", "dcds_s", "learned", "batch",
-                                                          "quality", "mvp", "e2e", "config1", "config2", "4k"}
+                                                          "quality", "mvp", "e2e", "config1", "config2", "config6",
+                                                          "4k"}
     if args.calib_copy:
         src = torch.ones(256 << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -596,7 +605,7 @@ def main():
         extra["mvp_stats_r7"] = mvp_leg(me, torch, cur, ref, args.steps, args.warmup)
     if "e2e" in legs:
         extra["end_to_end"] = e2e_leg(me, torch, seq_np, dev, args)
-    for k in (1, 2):
+    for k in (1, 2, 6):
         if "config%d" % k in legs:
             extra["config%d" % k] = small_config_leg(me, torch, dev, k, args)
     if "4k" in legs:

@@ -25,6 +25,13 @@ Recipes (sizes W x H):
   5  3840x2160, 60 frames, +-31, 64 objects, velocity Laplace(0, 8) /
      Laplace(0, 4) clipped to +-31; training sequences (1920x1088, 50 frames,
      the same law) use seeds 10000 + q, held-out ones 20000 + q.
+  6  CIF 352x288, 60 frames, +-7, near the paper's operating point (most
+     vectors zero, small motion, smooth texture): a static background of
+     blurred noise (sigma 3) stretched to standard deviation 30 around 128;
+     12 rectangles of side U{32..111} with texture of sigma 2 (the same
+     stretch, plus a uniform offset in -40..40), at uniform positions inside
+     the frame, velocity (rint Laplace(0, 2), rint Laplace(0, 1)) clipped to
+     +-7, moving off the frame rather than wrapping; N(0, 1) per frame.
 """
 from __future__ import annotations
 
@@ -175,6 +182,47 @@ def moving_sequence(spec: SequenceSpec) -> np.ndarray:
     return out
 
 
+def _stretched(rng: np.random.Generator, h: int, w: int, sigma: float) -> np.ndarray:
+    """Blurred noise rescaled to mean 128 and standard deviation 30."""
+    x = blurred_noise(rng, h, w, sigma)
+    c = x - x.mean()
+    return 128.0 + c * (30.0 / c.std())
+
+
+def paperlike_sequence(seed: int = 6, W: int = 352, H: int = 288, frames: int = 60, n_objects: int = 12,
+                       R: int = 7) -> np.ndarray:
+    """Config 6: a static smooth background and slowly moving smooth objects.
+
+    Object k is at p_k + v_k t (clipped by the frame, not wrapped), so inside
+    it the true vector is -v_k; the background's is (0, 0).
+    """
+    rng = _rng(seed)
+    bg = _stretched(rng, H, W, 3.0)
+    objs = []
+    for _ in range(n_objects):
+        w = int(rng.integers(32, 112))
+        h = int(rng.integers(32, 112))
+        tex = _stretched(rng, h, w, 2.0) + float(rng.uniform(-40.0, 40.0))
+        x = int(rng.integers(0, W - w))
+        y = int(rng.integers(0, H - h))
+        vx = int(np.clip(np.rint(rng.laplace(0.0, 2.0)), -R, R))
+        vy = int(np.clip(np.rint(rng.laplace(0.0, 1.0)), -R, R))
+        objs.append(_Obj(w, h, tex, x, y, vx, vy))
+    out = np.empty((frames, H, W), np.uint8)
+    for t in range(frames):
+        f = bg.astype(np.float32).copy()
+        for o in objs:
+            px, py = o.x + o.vx * t, o.y + o.vy * t
+            x0, y0 = max(px, 0), max(py, 0)
+            x1, y1 = min(px + o.w, W), min(py + o.h, H)
+            if x1 <= x0 or y1 <= y0:
+                continue
+            f[y0:y1, x0:x1] = o.tex[y0 - py:y1 - py, x0 - px:x1 - px]
+        f += rng.normal(0.0, 1.0, size=f.shape).astype(np.float32)
+        out[t] = _to_u8(f)
+    return out
+
+
 # Stream kinds of the batched configuration: (W, H, objects).
 BATCH_KINDS = [(176, 144, 2), (352, 288, 8), (1280, 720, 20), (1920, 1088, 32)]
 
@@ -210,11 +258,12 @@ CONFIGS = {
     3: ConfigInfo("1080p_1920x1088_60f_r15", 1920, 1088, 60, (16, 8), 15),
     4: ConfigInfo("batch_64streams_30f_r15", 0, 0, 30, (16,), 15),
     5: ConfigInfo("4k_3840x2160_60f_r31", 3840, 2160, 60, (16,), 31),
+    6: ConfigInfo("paperlike_cif_352x288_60f_r7", 352, 288, 60, (16,), 7),
 }
 
 
 def make_config(k: int, seed: int | None = None, frames: int | None = None):
-    """Frames [T, H, W] uint8 of config k (1, 2, 3 or 5); seed defaults to k."""
+    """Frames [T, H, W] uint8 of config k (1, 2, 3, 5 or 6); seed defaults to k."""
     seed = k if seed is None else seed
     if k == 1:
         cur, ref, _ = qcif_pair(seed)
@@ -225,6 +274,8 @@ def make_config(k: int, seed: int | None = None, frames: int | None = None):
         spec = SequenceSpec(1920, 1088, frames or 60, 32, "laplace4x2", 15, seed)
     elif k == 5:
         spec = SequenceSpec(3840, 2160, frames or 60, 64, "laplace8x4", 31, seed)
+    elif k == 6:
+        return paperlike_sequence(seed, frames=frames or 60)
     else:
         raise ValueError("config %r has no single sequence; use batch_streams" % k)
     return moving_sequence(spec)

@@ -1,5 +1,5 @@
 """What the trained proposer gains over DCDS without it, on every single-sequence
-workload (configs 1, 2, 3 and 5) and on held-out training-law sequences (never
+workload (configs 1, 2, 3, 5 and 6) and on held-out training-law sequences (never
 seen in training).
 
 Learned-start DCDS runs plain DCDS first and follows the proposed start only
@@ -50,6 +50,7 @@ def stats(seq, p, R):
 CASES = [
     ("config1_qcif_r7", lambda: make_config(1), 7, 1.01),
     ("config2_cif_r7", lambda: make_config(2, frames=12), 7, 1.01),
+    ("config6_paperlike_r7", lambda: make_config(6, frames=12), 7, 1.01),
     ("config3_1088p_r15", lambda: make_config(3, frames=4), 15, 0.95),
     ("config5_4k_r31", lambda: make_config(5, frames=3), 31, 0.9),
     ("held_out_1088p_q0_r31", lambda: training_sequence(0, frames=8, held_out=True), 31, 0.9),

@@ -119,6 +119,20 @@ def test_cif_multi_pair_call():
         assert_same(me.fullsearch(tc, tr, B, 7), oracle_pairs(oracle.fullsearch, cur, ref, B, 7), "cif fs")
 
 
+def test_paperlike_all_pairs():
+    """Config 6 (the paper's operating point), all 59 pairs in one call:
+    DCDS, DCDS^S and FS against the oracle."""
+    seq = make_config(6)
+    cur, ref = seq[1:], seq[:-1]
+    tseq = to_dev(seq)
+    tc, tr = tseq[1:], tseq[:-1]
+    say("case config 6, 59 pairs, B=16, R=7")
+    assert_same(me.dcds(tc, tr, 16, 7), oracle_pairs(oracle.dcds, cur, ref, 16, 7), "config 6 dcds")
+    assert_same(me.dcds(tc, tr, 16, 7, algo=me.ME_ALGO_DCDS_S),
+                oracle_pairs(oracle.dcds, cur, ref, 16, 7, variant=oracle.VARIANT_DCDS_S), "config 6 dcds_s")
+    assert_same(me.fullsearch(tc, tr, 16, 7), oracle_pairs(oracle.fullsearch, cur, ref, 16, 7), "config 6 fs")
+
+
 @pytest.mark.parametrize("case", range(24))
 def test_random_configurations(case):
     """Seeded random shapes, ranges, block sizes, pair counts, row pitches and
