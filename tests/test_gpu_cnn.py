@@ -174,13 +174,14 @@ def test_infer_ragged_views(frames, crop):
     assert np.array_equal(o.cpu().numpy(), eo)
 
 
-@pytest.mark.parametrize("shape", [(5, 256, 512), (4, 1088, 1920)])
+@pytest.mark.parametrize("shape", [(5, 256, 512), (4, 1088, 1920), (3, 2160, 3840)])
 def test_infer_tile_order(shape):
     """Grids that are multiples of 8 workgroups take the XCD-local tile
-    order (32 tiles on 32 workgroups; 405 tiles on at most 256): every block
-    still gets exactly forward() + decode."""
+    order (32 tiles on 32 workgroups; 405 tiles, and at 4K 1020 tiles with a
+    partial last tile row, on at most 256): every block still gets exactly
+    forward() + decode."""
     P, H, W = shape
-    seq = make_config(3, seed=21, frames=P)[:, :H, :W]
+    seq = (make_config(5, seed=21, frames=P) if H > 1088 else make_config(3, seed=21, frames=P))[:, :H, :W]
     p = me.Proposer(seed=11)
     cur, ref = dev(seq[1:]), dev(seq[:-1])
     head = p.forward(cur, ref).cpu().numpy()
