@@ -760,26 +760,36 @@ __global__ __launch_bounds__(kFusedThreads) void k_proposer_infer(
     int16_t* __restrict__ start, uint8_t* __restrict__ orient) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     uint32_t* x0 = reinterpret_cast<uint32_t*>(lds + kOffL2);  // the input tile, in layer 2's buffer
-    uint16_t* wl = reinterpret_cast<uint16_t*>(lds + kOffW);
     float* head = reinterpret_cast<float*>(lds + kOffHead);
     float* bl = reinterpret_cast<float*>(lds + kOffBias);
     const uint32_t a1 = lds_addr(lds), a2 = a1 + kOffL2, a3 = a1 + kOffL3, aw = a1 + kOffW, ah = a1 + kOffHead;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // Weights and biases, once.
-    {
-        const uint16_t* src[4] = {wf0, wf1, wf2, wf3};
-        const int off[4] = {0, kWOff1 / 2, kWOff2 / 2, kWOff3 / 2};
+    // Weights and biases, once.  Chunk c of row n of layer l (indices
+    // 8c .. 8c + 7 of W[n][.], 16 bytes) goes to the layer's LDS chunk
+    // c COUT + n.  The loads are issued here, the stores after the first
+    // input tile's loads (below), so that all of them are in flight together.
+    constexpr int kC0 = fwd_kp(kLayers[0].cin) / 8, kC1 = fwd_kp(kLayers[1].cin) / 8,
+                  kC2 = fwd_kp(kLayers[2].cin) / 8, kC3 = fwd_kp(kLayers[3].cin) / 8;
+    constexpr int kE0 = kLayers[0].cout * kC0, kE1 = kE0 + kLayers[1].cout * kC1, kE2 = kE1 + kLayers[2].cout * kC2,
+                  kE3 = kE2 + kLayers[3].cout * kC3;
+    constexpr int kPer = (kE3 + kFusedThreads - 1) / kFusedThreads;
+    v4u wq[kPer];
+    uint32_t wdst[kPer];
 #pragma unroll
-        for (int l = 0; l < 4; ++l) {
-            const int kp = fwd_kp(kLayers[l].cin), rows = kLayers[l].cout;
-            for (int i = threadIdx.x; i < rows * kp; i += blockDim.x) {
-                // W[n][k], k = 32 ks + 8 kq + j -> chunk (ks, kq, n), element j.
-                const int n = i / kp, k = i % kp;
-                wl[off[l] + ((k >> 3) * rows + n) * 8 + (k & 7)] = src[l][i];
-            }
-        }
-        for (int i = threadIdx.x; i < kBias; i += blockDim.x)
-            bl[i] = i < 16 ? b0[i] : i < 48 ? b1[i - 16] : i < 80 ? b2[i - 48] : b3[i - 80];
+    for (int j = 0; j < kPer; ++j) {
+        const int i = (int)threadIdx.x + j * kFusedThreads;
+        wdst[j] = 0xFFFFFFFFu;
+        if (i >= kE3) continue;
+        const int l = i < kE0 ? 0 : i < kE1 ? 1 : i < kE2 ? 2 : 3;
+        const int r = i - (l == 0 ? 0 : l == 1 ? kE0 : l == 2 ? kE1 : kE2);
+        const int cpr = l == 0 ? kC0 : l == 1 ? kC1 : l == 2 ? kC2 : kC3;
+        const int rows = l == 0 ? kLayers[0].cout : l == 1 ? kLayers[1].cout : l == 2 ? kLayers[2].cout
+                                                                                      : kLayers[3].cout;
+        const int n = r / cpr, c = r - n * cpr;
+        const uint16_t* src = l == 0 ? wf0 : l == 1 ? wf1 : l == 2 ? wf2 : wf3;
+        wq[j] = *reinterpret_cast<const v4u*>(src + (size_t)(n * cpr + c) * 8);
+        const int woff = l == 0 ? 0 : l == 1 ? kWOff1 : l == 2 ? kWOff2 : kWOff3;
+        wdst[j] = aw + (uint32_t)woff + 16u * (uint32_t)(c * rows + n);
     }
     const int H4 = 4 * Hb, W4 = 4 * Wb, H8 = 2 * Hb, W8 = 2 * Wb;
     const int tx = (Wb + kTB - 1) / kTB, ty = (Hb + kTB - 1) / kTB;
@@ -817,6 +827,11 @@ __global__ __launch_bounds__(kFusedThreads) void k_proposer_infer(
             input_store(x0, it, o);
         }
     }
+#pragma unroll
+    for (int j = 0; j < kPer; ++j)
+        if (wdst[j] != 0xFFFFFFFFu) *lds_ptr<v4u>(wdst[j]) = wq[j];
+    for (int i = threadIdx.x; i < kBias; i += blockDim.x)
+        bl[i] = i < 16 ? b0[i] : i < 48 ? b1[i - 16] : i < 80 ? b2[i - 48] : b3[i - 80];
     __syncthreads();
     for (int t = first; t < end; t += step) {
         int p, by0, bx0;
