@@ -745,6 +745,13 @@ __device__ __forceinline__ void input_store(uint32_t* x, int it, const uint32_t 
 // meanwhile.
 constexpr int kW3 = (kN3 * kN3 + 15) / 16;
 static_assert((kFusedThreads / 64 - kW3) * 64 >= kInItems, "input prefetch needs one item per idle lane");
+// L2 warming of the next tile's source rows: 3 dwords per raw row of each
+// frame (4 kN0 raw rows of 4 kN0 bytes; 128-byte lines).
+// One per thread (register budget): the touches past the thread count, the
+// last rows of the reference frame, are left out.
+constexpr int kWarm = 2 * 4 * kN0 * 3;
+constexpr int kWarmPer = 1;
+static_assert(4 * kN0 <= 176 + 4 && 4 * kN0 > 128, "bytes 0, 128 and 176 reach every line of a raw row");
 
 // grid: min(tiles, CUs) workgroups of kFusedThreads threads, kFusedLds bytes.
 // wf/bias: the packed layer weights ([COUT][KP], KP = fwd_kp(CIN)) and biases.
@@ -840,11 +847,36 @@ __global__ __launch_bounds__(kFusedThreads) void k_proposer_infer(
         const int y3 = by0 - 1, x3 = bx0 - 1;
         const int y2 = 2 * y3 - 1, x2 = 2 * x3 - 1;
         const int y1 = 2 * y2 - 1, x1 = 2 * x2 - 1;
+        // Warm the L2 with the next tile's source rows while layers 1 and 2
+        // run: one dword at bytes 0, 128 and 176 of each raw row's 180-byte
+        // stretch (so every 128-byte line of it), both frames, as far as one
+        // per thread goes; the fetch under layer 3 then reads from the L2.
+        // The dwords are only held, to keep the loads.
+        uint32_t warm[kWarmPer];
+        {
+            int pn, byn, bxn;
+            place(min(t + step, end - 1), pn, byn, bxn);
+            const bool next = t + step < end;
+#pragma unroll
+            for (int k = 0; k < kWarmPer; ++k) {
+                const int u = (int)threadIdx.x + k * kFusedThreads;
+                warm[k] = 0u;
+                if (!next || u >= kWarm) continue;
+                const int f = u / (kWarm / 2), rem = u - f * (kWarm / 2);
+                const int r = rem / 3, sgm = rem - 3 * r;
+                const int cy = min(max(4 * byn - 8 + (r >> 2), 0), H4 - 1);
+                const int rx = min(max(16 * bxn - 32 + (sgm == 0 ? 0 : sgm == 1 ? 128 : 176), 0), 4 * W4 - 4);
+                const uint8_t* frame = (f ? ref : cur) + (long long)pn * pair_stride;
+                warm[k] = *reinterpret_cast<const uint32_t*>(frame + (size_t)(4 * cy + (r & 3)) * pitch + rx);
+            }
+        }
         conv_tile<2, 16, 1, kN0, L1Tile, kN1, L1Tile, 2, true, false>(a2, a1, aw, bl, y1, x1, H4, W4);
         __syncthreads();
         conv_tile<16, 32, 2, kN1, L1Tile, kN2, L2Tile, 1, true, false>(a1, a2, aw + kWOff1, bl + 16, y2, x2, H8, W8);
         __syncthreads();
         conv_tile<32, 32, 2, kN2, L2Tile, kN3, L3Tile, 1, true, false>(a2, a3, aw + kWOff2, bl + 48, y3, x3, Hb, Wb);
+#pragma unroll
+        for (int k = 0; k < kWarmPer; ++k) asm volatile("" ::"v"(warm[k]));
         const int it = (int)threadIdx.x - 64 * kW3;
         const bool fetch = wave >= kW3 && t + step < end && it < kInItems;
         uint32_t o[4];
