@@ -507,7 +507,10 @@ constexpr int kBias = 16 + 32 + 32 + 4;
 // and the biases.
 constexpr int kOffL2 = L1Tile::kBytes, kOffL3 = kOffL2 + L2Tile::kBytes, kOffW = kOffL3 + L3Tile::kBytes;
 constexpr int kOffHead = kOffW + kWAll, kOffBias = kOffHead + 4 * 4 * kTB * kTB;
-constexpr size_t kFusedLds = (size_t)kOffBias + 4 * kBias;
+// A 16-byte slot per lane that stores with nothing to store go to (instead of
+// branching around them).
+constexpr int kOffDummy = (kOffBias + 4 * kBias + 15) / 16 * 16;
+constexpr size_t kFusedLds = (size_t)kOffDummy + 16 * 64;
 constexpr int kFusedThreads = 1024;
 static_assert(kOffL2 % 16 == 0 && kOffL3 % 16 == 0 && kOffW % 16 == 0 && kOffHead % 16 == 0,
               "16-byte aligned buffers");
@@ -516,7 +519,8 @@ static_assert(kFusedLds <= 160 * 1024, "one workgroup's LDS");
 // One 3x3 layer from an LDS tile to an LDS tile (or, for the head, to the
 // head buffer: fp32, 4 channels, 16 bytes per pixel).  LI/LO: input/output
 // layouts (LI unused for the 2-channel input: one dword per pixel, side NI);
-// NO: output tile side; wb: this layer's weight chunks; (oy0, ox0): output
+// NO: output tile side; wb: this layer's weight chunks; dummy: 16 bytes per lane
+// for stores with nothing to store; (oy0, ox0): output
 // tile origin in its layer's grid of Ho x Wo (outputs outside are written as
 // 0, the next layer's padding).  The weights are the MFMA row operand and 16
 // output pixels the column operand, so lane (m, kq) receives channels
@@ -530,7 +534,7 @@ static_assert(kFusedLds <= 160 * 1024, "one workgroup's LDS");
 // band) read inside LDS and are not stored.
 template <int CIN, int COUT, int S, int NI, class LI, int NO, class LO, int PARTS, bool RELU, bool HEAD>
 __device__ __forceinline__ void conv_tile(uint32_t ib, uint32_t ob, uint32_t wb, const float* bias, int oy0, int ox0,
-                                          int Ho, int Wo) {
+                                          int Ho, int Wo, uint32_t dummy) {
     constexpr int KP = fwd_kp(CIN);
     constexpr int KS = KP / 32;
     constexpr int NT = (COUT + 15) / 16;
@@ -654,10 +658,12 @@ __device__ __forceinline__ void conv_tile(uint32_t ib, uint32_t ob, uint32_t wb,
                                 kCache ? w[kCache ? ks : 0][t] : wk[kCache ? 0 : c][t], a[r][c], acc[r][t], 0, 0, 0);
                 }
             }
-            if (po >= MB) continue;
+            // A lane past its band, past the layer or without channels stores
+            // into its dummy slot instead of branching around the store.
+            const uint32_t dl = dummy + 16u * (uint32_t)lane;
 #pragma unroll
             for (int r = 0; r < PARTS; ++r) {
-                if (r > 0 && po + r * MB >= M) break;
+                const bool vr = po < MB && (r == 0 || po + r * MB < M);
                 // Outputs outside the layer's grid are the next layer's zero padding.
                 bool inside = true;
                 if constexpr (BORDER)
@@ -665,9 +671,9 @@ __device__ __forceinline__ void conv_tile(uint32_t ib, uint32_t ob, uint32_t wb,
                 const uint32_t od = obl + 16u * (uint32_t)po + (uint32_t)r * kOutBand;
 #pragma unroll
                 for (int t = 0; t < NT; ++t) {
-                    if (16 * t + 4 * kq >= COUT) continue;
+                    const bool vt = vr && 16 * t + 4 * kq < COUT;
                     if constexpr (HEAD) {
-                        *lds_ptr<v4f>(od) = acc[r][t];
+                        *lds_ptr<v4f>(vt ? od : dl) = acc[r][t];
                     } else {
                         // ReLU on the packed bf16 pair: one signed 16-bit max
                         // each (a negative value, -0 included, has its sign bit
@@ -679,7 +685,7 @@ __device__ __forceinline__ void conv_tile(uint32_t ib, uint32_t ob, uint32_t wb,
                         }
                         if (BORDER && !inside) o = v2u{0u, 0u};
                         // Channels 16 t + 4 kq .. + 3: plane 2 t + kq / 2.
-                        *lds_ptr<v2u>(od + 32u * (uint32_t)(t * LO::kPlane)) = o;
+                        *lds_ptr<v2u>(vt ? od + 32u * (uint32_t)(t * LO::kPlane) : dl) = o;
                     }
                 }
             }
@@ -769,7 +775,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_proposer_infer(
     uint32_t* x0 = reinterpret_cast<uint32_t*>(lds + kOffL2);  // the input tile, in layer 2's buffer
     float* head = reinterpret_cast<float*>(lds + kOffHead);
     float* bl = reinterpret_cast<float*>(lds + kOffBias);
-    const uint32_t a1 = lds_addr(lds), a2 = a1 + kOffL2, a3 = a1 + kOffL3, aw = a1 + kOffW, ah = a1 + kOffHead;
+    const uint32_t a1 = lds_addr(lds), a2 = a1 + kOffL2, a3 = a1 + kOffL3, aw = a1 + kOffW, ah = a1 + kOffHead,
+                   ad = a1 + kOffDummy;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     // Weights and biases, once.  Chunk c of row n of layer l (indices
     // 8c .. 8c + 7 of W[n][.], 16 bytes) goes to the layer's LDS chunk
@@ -847,6 +854,11 @@ __global__ __launch_bounds__(kFusedThreads) void k_proposer_infer(
         const int y3 = by0 - 1, x3 = bx0 - 1;
         const int y2 = 2 * y3 - 1, x2 = 2 * x3 - 1;
         const int y1 = 2 * y2 - 1, x1 = 2 * x2 - 1;
+        // Every earlier global access is complete here (the previous tile's
+        // fetch was consumed, its decode stores are the only ones left), so
+        // after this wait nothing but the warming loads below is pending, and
+        // layer 1 has no reason to wait for them (s_waitcnt vmcnt(0)).
+        __builtin_amdgcn_s_waitcnt(0x0F70);
         // Warm the L2 with the next tile's source rows while layers 1 and 2
         // run: one dword at bytes 0, 128 and 176 of each raw row's 180-byte
         // stretch (so every 128-byte line of it), both frames, as far as one
@@ -870,11 +882,11 @@ __global__ __launch_bounds__(kFusedThreads) void k_proposer_infer(
                 warm[k] = *reinterpret_cast<const uint32_t*>(frame + (size_t)(4 * cy + (r & 3)) * pitch + rx);
             }
         }
-        conv_tile<2, 16, 1, kN0, L1Tile, kN1, L1Tile, 2, true, false>(a2, a1, aw, bl, y1, x1, H4, W4);
+        conv_tile<2, 16, 1, kN0, L1Tile, kN1, L1Tile, 2, true, false>(a2, a1, aw, bl, y1, x1, H4, W4, ad);
         __syncthreads();
-        conv_tile<16, 32, 2, kN1, L1Tile, kN2, L2Tile, 1, true, false>(a1, a2, aw + kWOff1, bl + 16, y2, x2, H8, W8);
+        conv_tile<16, 32, 2, kN1, L1Tile, kN2, L2Tile, 1, true, false>(a1, a2, aw + kWOff1, bl + 16, y2, x2, H8, W8, ad);
         __syncthreads();
-        conv_tile<32, 32, 2, kN2, L2Tile, kN3, L3Tile, 1, true, false>(a2, a3, aw + kWOff2, bl + 48, y3, x3, Hb, Wb);
+        conv_tile<32, 32, 2, kN2, L2Tile, kN3, L3Tile, 1, true, false>(a2, a3, aw + kWOff2, bl + 48, y3, x3, Hb, Wb, ad);
 #pragma unroll
         for (int k = 0; k < kWarmPer; ++k) asm volatile("" ::"v"(warm[k]));
         const int it = (int)threadIdx.x - 64 * kW3;
@@ -888,7 +900,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_proposer_infer(
         }
         __syncthreads();
         // Head over the kTB x kTB blocks: local L3 (1 + i, 1 + j) is block (by0 + i, bx0 + j).
-        conv_tile<32, 4, 1, kN3, L3Tile, kTB, HeadTile, 1, false, true>(a3, ah, aw + kWOff3, bl + 80, by0, bx0, Hb, Wb);
+        conv_tile<32, 4, 1, kN3, L3Tile, kTB, HeadTile, 1, false, true>(a3, ah, aw + kWOff3, bl + 80, by0, bx0, Hb, Wb, ad);
         if (fetch) input_store(x0, it, o);
         __syncthreads();
         if (threadIdx.x < kTB * kTB) {
